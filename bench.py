@@ -1,0 +1,199 @@
+"""Throughput of the PCA holography hot path on one MI355X.
+
+Workload: one stack of 32 consecutive 1024 x 1024 uint16 interferograms per
+step (the paper-scale configuration), lambda 785 nm, pitch 20 um, z 0.3 m,
+principal components 2..31 kept, FP32 arithmetic.  A step is one hh_pipeline
+call: Fresnel FFT of every frame, covariance, Jacobi eigendecomposition,
+projection + |.|^2 image.  Inputs are seeded synthetic stacks, already resident
+in HBM; four distinct stacks are rotated so that no step reads an input that a
+previous step left in the 256 MB last-level cache.
+
+Prints ONE JSON line.  Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "interferograms/s through Fresnel+PCA (1024^2, 32-frame); % HBM roofline; p99 latency"
+NT, NY, NX, K_LO, K_HI = 32, 1024, 1024, 2, 31
+LAM, PITCH, Z = 785e-9, 20e-6, 0.3
+HBM_PEAK_GBS = 8000.0
+PAPER_INTERFEROGRAMS_PER_S = 20 * 32  # PCA of 32-frame stacks "up to 20 times per second" (Titan RTX)
+
+
+def algorithmic_bytes(kernel: str, launches_per_step: int) -> float:
+    """Compulsory HBM bytes of one launch of `kernel` for the 1024^2 x 32 stack.
+
+    Per pixel-frame: Fresnel row pass reads 2 (uint16) and writes 8 (complex64);
+    the in-place column pass reads 8 and writes 8; the Gram reads 8; the
+    projection reads 8 per pixel-frame and writes 4 per pixel.  Launches that
+    split a stack (frame groups) share its bytes evenly.
+    """
+    npf = NT * NY * NX
+    per_stack = {
+        "fresnel_rows": 10.0 * npf,
+        "fresnel_cols": 16.0 * npf,
+        "gram_partial": 8.0 * npf,
+        "project_complement": 8.0 * npf + 4.0 * NY * NX,
+        "project_direct": 8.0 * npf + 4.0 * NY * NX,
+    }.get(kernel)
+    if per_stack is None:
+        return float("nan")
+    return per_stack / max(1, launches_per_step)
+
+
+STACK_BYTES = NT * NY * NX * (2 + 3 * 8) + 4 * NY * NX  # input + H write + 2 H reads + image
+
+
+def cpu_baseline(frames_list):
+    """The FP64 oracle as it stands, single thread, on whole stacks (bounded sample)."""
+    import numpy as np
+    import oracle
+    try:
+        from threadpoolctl import threadpool_limits
+        lim = threadpool_limits(1)
+    except Exception:  # pragma: no cover
+        lim = None
+    times = []
+    t_budget = time.perf_counter()
+    for f in frames_list:
+        t0 = time.perf_counter()
+        oracle.pipeline_ref(f, LAM, Z, PITCH, K_LO, K_HI)
+        times.append(time.perf_counter() - t0)
+        if time.perf_counter() - t_budget > 20.0:
+            break
+    if lim is not None:
+        lim.unregister() if hasattr(lim, "unregister") else None
+    sec = float(np.median(times))
+    return {"value": NT / sec, "unit": "interferograms/s", "cores": 1, "kind": "oracle",
+            "sample": f"{len(times)} full 32x1024x1024 stack(s) through the FP64 numpy oracle "
+                      f"(generation excluded), median {sec:.2f} s/stack, BLAS and FFT on 1 thread"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=400)
+    ap.add_argument("--warmup", type=int, default=40)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (each stack is "
+              "independent: more GPUs would each run this same per-GPU workload).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2004_00923_amd.hh as hh
+    from paper_2004_00923_amd.synth import gen_stack
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    print("bench: generating 4 synthetic 32x1024x1024 stacks", file=sys.stderr, flush=True)
+    host = [gen_stack(s, NT, NY, NX) for s in range(4)]
+    frames = [torch.from_numpy(f).to(dev) for f in host]
+    p = hh.Params(nx=NX, ny=NY, nt=NT, k_lo=K_LO, k_hi=K_HI)
+    ws = hh.alloc_workspace(hh.workspace_bytes(p), dev)
+    img = torch.empty((NY, NX), dtype=torch.float32, device=dev)
+    info = torch.empty(1, dtype=torch.int32, device=dev)
+
+    def step(i):
+        hh.hh_pipeline(p, frames[i % 4], img, ws, info=info)
+
+    print(f"bench: warmup {args.warmup}", file=sys.stderr, flush=True)
+    for i in range(args.warmup):
+        step(i)
+    torch.cuda.synchronize()
+    sweeps = int(info.cpu()[0])
+
+    # timed region: exactly K steps, synchronised on both sides
+    print(f"bench: timing {args.steps} steps", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        step(i)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ms_per_step = 1e3 * elapsed / args.steps
+    value = NT * args.steps / elapsed
+
+    # per-kernel durations from HIP events recorded around each launch, over a
+    # second timed pass of the same K steps
+    hh.profile_reset()
+    hh.profile_enable(True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for i in range(args.steps):
+        step(i)
+    torch.cuda.synchronize()
+    prof_elapsed = time.perf_counter() - t1
+    hh.profile_enable(False)
+    prof = hh.profile_read()
+    hh.profile_reset()
+    kernels = {}
+    for name, (n, total_ms) in prof.items():
+        per_step = n / args.steps
+        avg_us = 1e3 * total_ms / n
+        b = algorithmic_bytes(name, round(per_step))
+        kernels[name] = {"launches_per_step": per_step, "avg_us": avg_us,
+                         "share": total_ms / (1e3 * prof_elapsed) if prof_elapsed > 0 else None,
+                         "gbs": (b / (avg_us * 1e-6) / 1e9) if b == b else None}
+    dom = max(kernels, key=lambda k: kernels[k]["avg_us"] * kernels[k]["launches_per_step"])
+    d = kernels[dom]
+    achieved = d["gbs"]
+    roofline = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": (achieved / HBM_PEAK_GBS) if achieved else None, "traffic": None,
+                "avg_us": d["avg_us"]}
+
+    # isolated per-stack latency (each stack waited for)
+    lat = []
+    for i in range(60):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        step(i)
+        e1.record()
+        torch.cuda.synchronize()
+        lat.append(e0.elapsed_time(e1))
+    lat = np.array(lat[10:])
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "interferograms/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": value / PAPER_INTERFEROGRAMS_PER_S,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "one 32x1024x1024 uint16 stack per step (4 seeded stacks rotated), "
+                               "lambda 785 nm, pitch 20 um, z 0.3 m, PCs 2..31, FP32",
+                   "stacks_per_s": value / NT, "precision": "fp32", "jacobi_sweeps": sweeps},
+        "roofline": roofline,
+        "stack_roofline": {"bytes_per_stack": STACK_BYTES,
+                           "achieved": STACK_BYTES / (ms_per_step * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
+                           "unit": "GB/s", "frac": STACK_BYTES / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS},
+        "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
+        "kernels": kernels,
+    }
+    if not args.no_cpu:
+        print("bench: timing the FP64 oracle on the host", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(host[:2])
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

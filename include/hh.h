@@ -1,0 +1,196 @@
+/*
+ * hh.h — C ABI of the PCA digital-holography hot path on AMD Instinct MI355X (gfx950).
+ *
+ * Method: Puyo et al., "Real-time digital holography of the retina by principal
+ * component analysis" (arXiv:2004.00923).  A stack of n_t consecutive 16-bit
+ * inline interferograms becomes one power-Doppler image in five steps:
+ *   (a) Fresnel propagation of every frame, Eq. (1): chirp multiply + 2D FFT;
+ *   (b) the n_t x n_t time-lagged covariance C = H^{t*} H, Eq. (4);
+ *   (c) its eigendecomposition C = V Lambda V^{t*}, Eq. (5);
+ *   (d) projection of the stack on the eigenvectors, H_breve = H V I_f, Eq. (6);
+ *   (e) the image M(x,y) = sum over kept components of |H_breve|^2, Eq. (7).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Array pointers are DEVICE pointers on the current HIP device, owned by the
+ *    caller; the library never frees or keeps them.  All arrays are dense,
+ *    C-order, without padding.
+ *  - Complex arrays are interleaved (re, im): "complex64" = 2 x float,
+ *    "complex128" = 2 x double.
+ *  - A stack is frame-major [n][ny][nx] (nx is the fast axis); the paper's
+ *    space-time matrix H (n_x n_y rows, n_t columns) is its transpose view:
+ *    H[p][t] = stack[t][p], p = y * nx + x.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).  Work is
+ *    enqueued on it and the call returns without waiting for the device.
+ *  - Host-side failures (bad parameters, NULL pointers, a workspace that is too
+ *    small, an unsupported size) return synchronously and enqueue nothing.
+ *    A failing HIP launch returns HH_E_DEVICE.  The text of the last failure on
+ *    the calling thread is in hh_last_error().
+ *  - Device tables (chirps, twiddles) are built on the first call for a given
+ *    (device, wavelength, distance, pitch, nx, ny) and cached until
+ *    hh_plan_cache_clear(); that first call allocates and copies synchronously.
+ *  - Entry points never synchronise the host with the device, except that
+ *    first-call table build.
+ */
+#ifndef HH_H
+#define HH_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t hh_status;
+
+enum {
+  HH_OK = 0,
+  HH_E_INVALID = 1,       /* bad parameter or NULL pointer */
+  HH_E_UNSUPPORTED = 2,   /* valid but not implemented (size, precision form) */
+  HH_E_WORKSPACE = 3,     /* workspace NULL or smaller than required */
+  HH_E_DEVICE = 4,        /* a HIP runtime call or kernel launch failed */
+  HH_E_NOT_CONVERGED = 5  /* reserved for host-side reporting of info < 0 */
+};
+
+/* Arithmetic of the covariance and projection contractions. */
+enum {
+  HH_FP32 = 0,      /* FP32 products, short FP32 partial sums, FP64 reduction */
+  HH_BF16 = 1,      /* BF16 operands on MFMA, FP32 accumulation */
+  HH_FP16 = 2,      /* FP16 operands (power-of-two stack scale) on MFMA */
+  HH_BF16X3 = 3,    /* hi/lo BF16 split, three MFMA products */
+  HH_FP16X3 = 4,    /* hi/lo FP16 split, three MFMA products */
+  HH_FP8E4M3 = 5    /* OCP e4m3 operands, per-frame power-of-two scales */
+};
+
+/* How the image of Eq. (7) is evaluated (same result up to rounding). */
+enum {
+  HH_PROJ_AUTO = 0,        /* the cheaper of the two below */
+  HH_PROJ_DIRECT = 1,      /* sum over kept k of |sum_t H[p][t] V[t][k]|^2, FP32 */
+  HH_PROJ_COMPLEMENT = 2   /* sum_t |H[p][t]|^2 - sum over dropped k of |.|^2, FP64
+                              (V unitary, Eq. (5); exact reformulation) */
+};
+
+typedef struct {
+  double wavelength_m;  /* lambda > 0 (laser wavelength, set-up section) */
+  double distance_m;    /* z != 0: sensor-to-object distance of Eq. (1) */
+  double pitch_m;       /* d > 0: square pixel pitch (set-up section) */
+  int32_t nx, ny;       /* frame width (fast axis) and height: powers of two, 8..4096 */
+  int32_t nt;           /* stack length n_t, 2..64 */
+  int32_t k_lo, k_hi;   /* kept components of I_f (Eq. (6)), 0-based, inclusive,
+                           counted in DESCENDING eigenvalue order: 0 <= k_lo <= k_hi < nt.
+                           The paper's 1-based ascending n1..n2 maps to nt-n2..nt-n1. */
+  int32_t precision;    /* HH_FP32 ... (contractions of steps (b) and (d)) */
+  int32_t proj_mode;    /* HH_PROJ_AUTO / _DIRECT / _COMPLEMENT */
+  int32_t reserved;     /* must be 0 */
+} hh_params;
+
+/* Bytes of device workspace hh_pipeline needs for *p (0 if *p is invalid). */
+size_t hh_workspace_bytes(const hh_params *p);
+
+/* Bytes of device workspace hh_covariance needs for *p (0 if *p is invalid). */
+size_t hh_covariance_workspace_bytes(const hh_params *p);
+
+/*
+ * Step (a), Eq. (1): Fresnel holograms of `nframes` frames.
+ *   frames : uint16 [nframes][ny][nx] raw interferograms (no offset removed).
+ *   holo   : complex64 [nframes][ny][nx] output,
+ *            holo[t][v][u] = sum_{n,m} I_t[n][m] c[n][m] exp(-2 pi i (u m/nx + v n/ny)),
+ *            c[n][m] = exp(-i pi d^2 ((m - nx/2)^2 + (n - ny/2)^2) / (lambda z)).
+ *            Forward, unnormalised DFT, DC at index 0; the constant prefactor and
+ *            the output-plane chirp of Eq. (1) are omitted.
+ * Only wavelength, distance, pitch, nx, ny of *p are used.  nframes >= 0 (0 = no-op).
+ */
+hh_status hh_fresnel(const hh_params *p, const uint16_t *frames, int32_t nframes,
+                     float *holo, void *stream);
+
+/*
+ * Step (b), Eq. (4): C = H^{t*} H of a hologram stack.
+ *   holo : complex64 [nt][ny][nx] (e.g. the output of hh_fresnel).
+ *   cov  : complex128 [nt][nt] output, C[s][t] = sum_p conj(H_s[p]) H_t[p]; exactly
+ *          Hermitian (Im C[s][s] = 0, C[t][s] = conj C[s][t]); no centring, no 1/N.
+ *   workspace : device buffer of at least hh_covariance_workspace_bytes(p) bytes.
+ * Uses nx, ny, nt, precision of *p.
+ */
+hh_status hh_covariance(const hh_params *p, const float *holo, double *cov,
+                        void *workspace, size_t ws_bytes, void *stream);
+
+/*
+ * Step (c), Eq. (5): Hermitian eigendecomposition C = V Lambda V^{t*} in FP64
+ * (parallel cyclic Jacobi, one workgroup).
+ *   nt    : 2..64.
+ *   cov   : complex128 [nt][nt] Hermitian input (only read).
+ *   evals : float64 [nt] output, DESCENDING.
+ *   evecs : complex128 [nt][nt] output, evecs[t][k] = V[t][k] (column k is the
+ *           eigenvector of evals[k]); each column's phase is fixed so that its
+ *           largest-modulus entry (lowest row among ties within 1e-12) is real > 0.
+ *   info  : int32 [1] output on the device: number of Jacobi sweeps (>= 0), or -1
+ *           if the iteration did not converge within the sweep limit (outputs
+ *           are then the last iterate).
+ */
+hh_status hh_eigh(int32_t nt, const double *cov, double *evals, double *evecs,
+                  int32_t *info, void *stream);
+
+/* hh_eigh with an explicit sweep limit (max_sweeps >= 0; hh_eigh uses 40). */
+hh_status hh_eigh_ex(int32_t nt, const double *cov, double *evals, double *evecs,
+                     int32_t *info, int32_t max_sweeps, void *stream);
+
+/*
+ * Steps (d)+(e), Eqs. (6)-(7): the power image of the kept components, with the
+ * projection fused into the |.|^2 sum (the components are never stored).
+ *   holo  : complex64 [nt][ny][nx].
+ *   evecs : complex128 [nt][nt], evecs[t][k] = V[t][k] (as written by hh_eigh).
+ *   image : float32 [ny][nx] output, M[p] = sum_{k=k_lo..k_hi} |sum_t H[p][t] V[t][k]|^2.
+ * Uses nx, ny, nt, k_lo, k_hi, precision, proj_mode of *p.  HH_PROJ_COMPLEMENT
+ * and HH_PROJ_AUTO rely on V being unitary (as hh_eigh returns it).
+ */
+hh_status hh_project_render(const hh_params *p, const float *holo, const double *evecs,
+                            float *image, void *stream);
+
+/*
+ * Steps (a)-(e) on one stack, in the paper's order, all on `stream`.
+ *   frames : uint16 [nt][ny][nx].
+ *   image  : float32 [ny][nx] output (Eq. (7)).
+ *   evals, evecs, info : optional outputs as in hh_eigh (NULL = not returned).
+ *   workspace : at least hh_workspace_bytes(p) bytes; holds the hologram stack
+ *               and the covariance partial sums.  It must not be shared by calls
+ *               that may run concurrently.
+ */
+hh_status hh_pipeline(const hh_params *p, const uint16_t *frames, float *image,
+                      double *evals, double *evecs, int32_t *info,
+                      void *workspace, size_t ws_bytes, void *stream);
+
+/*
+ * Fourier demodulation, Eqs. (8)-(9) (the paper's comparison method):
+ *   image[p] = sum_{f=k_lo..k_hi} |sum_t H[p][t] W[t][f]|^2,
+ *   W[t][f] = exp(-2 i pi t f / nt) / sqrt(nt), 0-based frequency indices
+ *   (the paper's 1-based n1..n2 maps to n1-1..n2-1).
+ * Uses nx, ny, nt, k_lo, k_hi, proj_mode of *p.
+ */
+hh_status hh_fourier_render(const hh_params *p, const float *holo, float *image, void *stream);
+
+/* Static text for a status code. */
+const char *hh_status_string(hh_status s);
+
+/* Detail of the last failing call on the calling thread ("" if none). */
+const char *hh_last_error(void);
+
+/* Free every cached device table (call only when no work using them is in flight). */
+void hh_plan_cache_clear(void);
+
+/*
+ * Kernel timing for measurement.  While enabled (on != 0), each kernel the
+ * library launches is bracketed by two HIP events recorded on its own stream.
+ * hh_profile_read waits for those events and writes a JSON object
+ * {"kernel": [launches, total_ms], ...} into buf (NUL-terminated, truncated to
+ * len); it returns the number of bytes needed.  hh_profile_reset forgets all.
+ */
+void hh_profile_enable(int32_t on);
+int32_t hh_profile_read(char *buf, int32_t len);
+void hh_profile_reset(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HH_H */

@@ -1,0 +1,180 @@
+// Step (a), Eq. (1): Fresnel holograms = 2D FFT of (interferogram x input-plane chirp).
+//
+// Two kernels per frame group:
+//   fresnel_rows : uint16 load -> FP32 -> chirp a[m] b[n] -> row FFT -> complex64 out
+//   fresnel_cols : in-place column FFT on the row-transformed frames
+// Each 1D transform is a two-pass Stockham FFT: a radix-E DFT in registers per
+// thread, one LDS exchange, then radix-T DFTs with W_N twiddles from a table
+// built in FP64 on the host.
+#include "fft_common.h"
+#include "hh_internal.h"
+
+namespace hh {
+namespace {
+
+// Rows per workgroup: 256 threads where the LDS exchange stays near 68 KiB.
+template <int N>
+constexpr int rows_per_wg() {
+  constexpr int T = FftShape<N>::T;
+  int r = 256 / T;
+  while (r > 1 && r * FftShape<N>::PADN * 8 > 70000) r >>= 1;
+  return r;
+}
+
+// Columns per workgroup (the fast-axis width of one coalesced strip).
+template <int N>
+constexpr int cols_per_wg() {
+  constexpr int T = FftShape<N>::T;
+  if (T == 1) return 64;
+  int w = 256 / T;
+  if (w < 16) w = 16;
+  while (w > 1 && w * FftShape<N>::PADN * 8 > 140000) w >>= 1;
+  return w;
+}
+
+template <int N, int ROWS>
+__global__ __launch_bounds__(ROWS *FftShape<N>::T) void fresnel_rows(
+    const uint16_t *__restrict__ frames, int ny, const float2 *__restrict__ chirp_x,
+    const float2 *__restrict__ chirp_y, const float2 *__restrict__ tw, float2 *__restrict__ out) {
+  constexpr int E = FftShape<N>::E, T = FftShape<N>::T;
+  const int t = threadIdx.x % T;
+  const int r = threadIdx.x / T;
+  const int row = blockIdx.x * ROWS + r;
+  const bool live = row < ny;
+  const size_t base = ((size_t)blockIdx.y * ny + (live ? row : 0)) * N;
+
+  float2 v[E];
+  {
+    const float2 cy = chirp_y[live ? row : 0];
+#pragma unroll
+    for (int i = 0; i < E; ++i) {
+      const int m = t + T * i;
+      const float val = live ? (float)frames[base + m] : 0.0f;
+      const float2 c = cmul(chirp_x[m], cy);
+      v[i] = make_float2(val * c.x, val * c.y);
+    }
+  }
+  dft_reg<E>(v);
+  if constexpr (T > 1) {
+    __shared__ float2 lds[ROWS * FftShape<N>::PADN];
+    float2 *my = lds + r * FftShape<N>::PADN;
+#pragma unroll
+    for (int k = 0; k < E; ++k) my[t * (E + 1) + k] = v[k];
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < E; ++i) {
+      const int e = t + T * i;
+      v[i] = my[e + e / E];
+    }
+    fft_pass1<N>(v, t, tw);
+  }
+  if (live) {
+#pragma unroll
+    for (int i = 0; i < E; ++i) out[base + t + T * i] = v[i];
+  }
+}
+
+template <int N, int W>
+__global__ __launch_bounds__(W *FftShape<N>::T) void fresnel_cols(float2 *__restrict__ data, int nx,
+                                                                 const float2 *__restrict__ tw) {
+  constexpr int E = FftShape<N>::E, T = FftShape<N>::T;
+  const int c = threadIdx.x % W;
+  const int t = threadIdx.x / W;
+  const int col = blockIdx.x * W + c;
+  const bool live = col < nx;
+  float2 *base = data + (size_t)blockIdx.y * N * nx + (live ? col : 0);
+
+  float2 v[E];
+#pragma unroll
+  for (int i = 0; i < E; ++i) v[i] = live ? base[(size_t)(t + T * i) * nx] : make_float2(0.f, 0.f);
+  dft_reg<E>(v);
+  if constexpr (T > 1) {
+    __shared__ float2 lds[W * FftShape<N>::PADN];
+#pragma unroll
+    for (int k = 0; k < E; ++k) lds[(t * (E + 1) + k) * W + c] = v[k];
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < E; ++i) {
+      const int e = t + T * i;
+      v[i] = lds[(e + e / E) * W + c];
+    }
+    fft_pass1<N>(v, t, tw);
+  }
+  if (live) {
+#pragma unroll
+    for (int i = 0; i < E; ++i) base[(size_t)(t + T * i) * nx] = v[i];
+  }
+}
+
+template <int N>
+hipError_t rows_n(const Plan &pl, const uint16_t *frames, int nframes, float2 *out, hipStream_t s) {
+  constexpr int R = rows_per_wg<N>();
+  dim3 grid((pl.ny + R - 1) / R, nframes);
+  ProfScope ps("fresnel_rows", s);
+  hipLaunchKernelGGL((fresnel_rows<N, R>), grid, dim3(R * FftShape<N>::T), 0, s, frames, pl.ny,
+                     pl.chirp_x, pl.chirp_y, pl.tw_x, out);
+  return hipGetLastError();
+}
+
+template <int N>
+hipError_t cols_n(const Plan &pl, int nframes, float2 *data, hipStream_t s) {
+  constexpr int W = cols_per_wg<N>();
+  dim3 grid((pl.nx + W - 1) / W, nframes);
+  ProfScope ps("fresnel_cols", s);
+  hipLaunchKernelGGL((fresnel_cols<N, W>), grid, dim3(W * FftShape<N>::T), 0, s, data, pl.nx, pl.tw_y);
+  return hipGetLastError();
+}
+
+hipError_t rows_dispatch(const Plan &pl, const uint16_t *f, int n, float2 *o, hipStream_t s) {
+  switch (pl.nx) {
+    case 8: return rows_n<8>(pl, f, n, o, s);
+    case 16: return rows_n<16>(pl, f, n, o, s);
+    case 32: return rows_n<32>(pl, f, n, o, s);
+    case 64: return rows_n<64>(pl, f, n, o, s);
+    case 128: return rows_n<128>(pl, f, n, o, s);
+    case 256: return rows_n<256>(pl, f, n, o, s);
+    case 512: return rows_n<512>(pl, f, n, o, s);
+    case 1024: return rows_n<1024>(pl, f, n, o, s);
+    case 2048: return rows_n<2048>(pl, f, n, o, s);
+    case 4096: return rows_n<4096>(pl, f, n, o, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t cols_dispatch(const Plan &pl, int n, float2 *d, hipStream_t s) {
+  switch (pl.ny) {
+    case 8: return cols_n<8>(pl, n, d, s);
+    case 16: return cols_n<16>(pl, n, d, s);
+    case 32: return cols_n<32>(pl, n, d, s);
+    case 64: return cols_n<64>(pl, n, d, s);
+    case 128: return cols_n<128>(pl, n, d, s);
+    case 256: return cols_n<256>(pl, n, d, s);
+    case 512: return cols_n<512>(pl, n, d, s);
+    case 1024: return cols_n<1024>(pl, n, d, s);
+    case 2048: return cols_n<2048>(pl, n, d, s);
+    case 4096: return cols_n<4096>(pl, n, d, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+}  // namespace
+
+// Frames are processed in groups so that a group's row-transformed frames are
+// still in the last-level cache when the column pass reads them back.
+hipError_t launch_fresnel(const Plan &pl, const uint16_t *frames, int nframes, float2 *holo,
+                          hipStream_t s) {
+  const size_t frame_bytes = (size_t)pl.nx * pl.ny * sizeof(float2);
+  int group = (int)((64u << 20) / frame_bytes);  // about 64 MiB of holograms per group
+  if (group < 1) group = 1;
+  for (int f0 = 0; f0 < nframes; f0 += group) {
+    const int n = nframes - f0 < group ? nframes - f0 : group;
+    const size_t off = (size_t)f0 * pl.nx * pl.ny;
+    hipError_t e = rows_dispatch(pl, frames + off, n, holo + off, s);
+    if (e != hipSuccess) return e;
+    e = cols_dispatch(pl, n, holo + off, s);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+}  // namespace hh

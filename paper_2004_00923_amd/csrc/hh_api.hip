@@ -1,0 +1,438 @@
+// C ABI of libhh: host-side validation, device-table cache, workspace layout and
+// the ordered launch of the hot-path kernels.  No entry point waits for the
+// device except the first-call table build of a configuration.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "hh_internal.h"
+
+namespace hh {
+
+// ---------------------------------------------------------------- errors ----
+static thread_local std::string g_err;
+
+void set_error(const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+}
+
+static hh_status fail(hh_status s, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return s;
+}
+
+static hh_status device_fail(hipError_t e, const char *where) {
+  return fail(HH_E_DEVICE, "%s: %s", where, hipGetErrorString(e));
+}
+
+// -------------------------------------------------------------- profiler ----
+namespace {
+struct ProfRec {
+  std::string name;
+  hipEvent_t a, b;
+};
+std::mutex g_prof_mu;
+bool g_prof_on = false;
+std::vector<ProfRec> g_prof;
+std::vector<hipEvent_t> g_prof_pool;
+
+hipEvent_t prof_event() {
+  if (!g_prof_pool.empty()) {
+    hipEvent_t e = g_prof_pool.back();
+    g_prof_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+}  // namespace
+
+ProfScope::ProfScope(const char *n, hipStream_t s) : name(n), stream(s) {
+  std::lock_guard<std::mutex> g(g_prof_mu);
+  if (!g_prof_on) return;
+  hipEvent_t e = prof_event();
+  if (e && hipEventRecord(e, s) == hipSuccess) ev0 = e;
+}
+
+ProfScope::~ProfScope() {
+  if (!ev0) return;
+  std::lock_guard<std::mutex> g(g_prof_mu);
+  hipEvent_t e = prof_event();
+  if (e && hipEventRecord(e, stream) == hipSuccess) g_prof.push_back({name, (hipEvent_t)ev0, e});
+}
+
+// ----------------------------------------------------------- plan cache ----
+namespace {
+using PlanKey = std::tuple<int, double, double, double, int, int>;
+std::mutex g_plan_mu;
+std::map<PlanKey, Plan> g_plans;
+std::map<std::pair<int, int>, double *> g_dft;
+
+bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+
+// exp(-i alpha (j - n/2)^2), phase formed from an exact integer square in FP64
+std::vector<float2> chirp_table(int n, double alpha) {
+  std::vector<float2> t(n);
+  for (int j = 0; j < n; ++j) {
+    const long long d = (long long)j - n / 2;
+    const double ph = alpha * (double)(d * d);
+    t[j] = make_float2((float)std::cos(ph), (float)-std::sin(ph));
+  }
+  return t;
+}
+
+// W_n^j = exp(-2 pi i j / n), from the exact rational angle j/n in FP64
+std::vector<float2> twiddle_table(int n) {
+  std::vector<float2> t(n);
+  const double two_pi = 6.283185307179586476925286766559;
+  for (int j = 0; j < n; ++j) {
+    const double ang = two_pi * (double)j / (double)n;
+    t[j] = make_float2((float)std::cos(ang), (float)-std::sin(ang));
+  }
+  return t;
+}
+
+hipError_t upload(float2 **dst, const std::vector<float2> &src) {
+  hipError_t e = hipMalloc(dst, src.size() * sizeof(float2));
+  if (e != hipSuccess) return e;
+  return hipMemcpy(*dst, src.data(), src.size() * sizeof(float2), hipMemcpyHostToDevice);
+}
+}  // namespace
+
+const Plan *get_plan(const hh_params &p) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) {
+    set_error("hipGetDevice: %s", hipGetErrorString(e));
+    return nullptr;
+  }
+  PlanKey key{dev, p.wavelength_m, p.distance_m, p.pitch_m, p.nx, p.ny};
+  std::lock_guard<std::mutex> g(g_plan_mu);
+  auto it = g_plans.find(key);
+  if (it != g_plans.end()) return &it->second;
+  const double alpha = M_PI * p.pitch_m * p.pitch_m / (p.wavelength_m * p.distance_m);
+  Plan pl;
+  pl.device = dev;
+  pl.nx = p.nx;
+  pl.ny = p.ny;
+  if ((e = upload(&pl.chirp_x, chirp_table(p.nx, alpha))) != hipSuccess ||
+      (e = upload(&pl.chirp_y, chirp_table(p.ny, alpha))) != hipSuccess ||
+      (e = upload(&pl.tw_x, twiddle_table(p.nx))) != hipSuccess ||
+      (e = upload(&pl.tw_y, twiddle_table(p.ny))) != hipSuccess) {
+    set_error("plan tables: %s", hipGetErrorString(e));
+    (void)hipFree(pl.chirp_x);
+    (void)hipFree(pl.chirp_y);
+    (void)hipFree(pl.tw_x);
+    (void)hipFree(pl.tw_y);
+    return nullptr;
+  }
+  return &g_plans.emplace(key, pl).first->second;
+}
+
+const double *get_dft_basis(int nt) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+  std::lock_guard<std::mutex> g(g_plan_mu);
+  auto it = g_dft.find({dev, nt});
+  if (it != g_dft.end()) return it->second;
+  std::vector<double> w(2 * (size_t)nt * nt);
+  const double two_pi = 6.283185307179586476925286766559, sc = 1.0 / std::sqrt((double)nt);
+  for (int t = 0; t < nt; ++t)
+    for (int f = 0; f < nt; ++f) {
+      const long long tf = ((long long)t * f) % nt;  // exact reduction of the angle
+      const double ang = two_pi * (double)tf / (double)nt;
+      w[2 * ((size_t)t * nt + f)] = std::cos(ang) * sc;
+      w[2 * ((size_t)t * nt + f) + 1] = -std::sin(ang) * sc;
+    }
+  double *d = nullptr;
+  if (hipMalloc(&d, w.size() * sizeof(double)) != hipSuccess) return nullptr;
+  if (hipMemcpy(d, w.data(), w.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess) {
+    (void)hipFree(d);
+    return nullptr;
+  }
+  g_dft[{dev, nt}] = d;
+  return d;
+}
+
+// ------------------------------------------------------------ validation ----
+namespace {
+hh_status check_optics(const hh_params *p) {
+  if (!p) return fail(HH_E_INVALID, "params is NULL");
+  if (!(std::isfinite(p->wavelength_m) && p->wavelength_m > 0))
+    return fail(HH_E_INVALID, "wavelength_m must be finite and > 0");
+  if (!(std::isfinite(p->distance_m) && p->distance_m != 0))
+    return fail(HH_E_INVALID, "distance_m must be finite and != 0");
+  if (!(std::isfinite(p->pitch_m) && p->pitch_m > 0)) return fail(HH_E_INVALID, "pitch_m must be finite and > 0");
+  return HH_OK;
+}
+
+hh_status check_shape(const hh_params *p) {
+  if (!p) return fail(HH_E_INVALID, "params is NULL");
+  if (p->nx <= 0 || p->ny <= 0) return fail(HH_E_INVALID, "nx, ny must be > 0");
+  if (!is_pow2(p->nx) || !is_pow2(p->ny) || p->nx < 8 || p->ny < 8 || p->nx > 4096 || p->ny > 4096)
+    return fail(HH_E_UNSUPPORTED, "nx=%d ny=%d: frame sides must be powers of two in [8, 4096]", p->nx, p->ny);
+  if (p->reserved != 0) return fail(HH_E_INVALID, "reserved field must be 0");
+  return HH_OK;
+}
+
+hh_status check_stack(const hh_params *p) {
+  hh_status s = check_shape(p);
+  if (s) return s;
+  if (p->nt < 2 || p->nt > 64) return fail(HH_E_UNSUPPORTED, "nt=%d: stack length must be in [2, 64]", p->nt);
+  return HH_OK;
+}
+
+hh_status check_select(const hh_params *p) {
+  if (!(0 <= p->k_lo && p->k_lo <= p->k_hi && p->k_hi < p->nt))
+    return fail(HH_E_INVALID, "kept range k_lo=%d k_hi=%d must satisfy 0 <= k_lo <= k_hi < nt=%d", p->k_lo,
+                p->k_hi, p->nt);
+  if (p->proj_mode < HH_PROJ_AUTO || p->proj_mode > HH_PROJ_COMPLEMENT)
+    return fail(HH_E_INVALID, "proj_mode=%d unknown", p->proj_mode);
+  return HH_OK;
+}
+
+hh_status check_precision(const hh_params *p) {
+  if (p->precision < HH_FP32 || p->precision > HH_FP8E4M3) return fail(HH_E_INVALID, "precision=%d unknown", p->precision);
+  if (p->precision != HH_FP32) return fail(HH_E_UNSUPPORTED, "precision form %d not built", p->precision);
+  return HH_OK;
+}
+
+bool aligned(const void *ptr, size_t a) { return ((uintptr_t)ptr % a) == 0; }
+
+struct PipeLayout {
+  GramLayout g;
+  size_t holo = 0, part = 0, part2 = 0, cov = 0, evals = 0, evecs = 0, info = 0, total = 0;
+};
+
+PipeLayout pipe_layout(const hh_params *p) {
+  PipeLayout L;
+  const long long npix = (long long)p->nx * p->ny;
+  L.g = gram_layout(p->nt, npix);
+  size_t o = 0;
+  L.holo = o; o = align_up(o + (size_t)p->nt * npix * sizeof(float2));
+  L.part = o; o = align_up(o + L.g.partial_bytes);
+  L.part2 = o; o = align_up(o + L.g.partial2_bytes);
+  L.cov = o; o = align_up(o + (size_t)p->nt * p->nt * 2 * sizeof(double));
+  L.evals = o; o = align_up(o + (size_t)p->nt * sizeof(double));
+  L.evecs = o; o = align_up(o + (size_t)p->nt * p->nt * 2 * sizeof(double));
+  L.info = o; o = align_up(o + sizeof(int));
+  L.total = o;
+  return L;
+}
+
+size_t cov_ws_bytes(const hh_params *p) {
+  const GramLayout g = gram_layout(p->nt, (long long)p->nx * p->ny);
+  return align_up(g.partial_bytes) + align_up(g.partial2_bytes);
+}
+}  // namespace
+
+}  // namespace hh
+
+using namespace hh;
+
+extern "C" {
+
+const char *hh_status_string(hh_status s) {
+  switch (s) {
+    case HH_OK: return "ok";
+    case HH_E_INVALID: return "invalid argument";
+    case HH_E_UNSUPPORTED: return "unsupported";
+    case HH_E_WORKSPACE: return "workspace too small";
+    case HH_E_DEVICE: return "device error";
+    case HH_E_NOT_CONVERGED: return "eigensolver did not converge";
+  }
+  return "unknown status";
+}
+
+const char *hh_last_error(void) { return g_err.c_str(); }
+
+size_t hh_workspace_bytes(const hh_params *p) {
+  if (check_optics(p) || check_stack(p) || check_select(p)) return 0;
+  return pipe_layout(p).total;
+}
+
+size_t hh_covariance_workspace_bytes(const hh_params *p) {
+  if (check_stack(p)) return 0;
+  return cov_ws_bytes(p);
+}
+
+hh_status hh_fresnel(const hh_params *p, const uint16_t *frames, int32_t nframes, float *holo, void *stream) {
+  hh_status st;
+  if ((st = check_optics(p)) || (st = check_shape(p))) return st;
+  if (nframes < 0 || nframes > 65535) return fail(HH_E_INVALID, "nframes=%d must be in [0, 65535]", nframes);
+  if (nframes == 0) return HH_OK;
+  if (!frames || !holo) return fail(HH_E_INVALID, "frames and holo must be non-NULL");
+  if (!aligned(frames, 2) || !aligned(holo, 16)) return fail(HH_E_INVALID, "frames/holo misaligned");
+  const Plan *pl = get_plan(*p);
+  if (!pl) return HH_E_DEVICE;
+  hipError_t e = launch_fresnel(*pl, frames, nframes, reinterpret_cast<float2 *>(holo), (hipStream_t)stream);
+  if (e != hipSuccess) return device_fail(e, "hh_fresnel");
+  return HH_OK;
+}
+
+hh_status hh_covariance(const hh_params *p, const float *holo, double *cov, void *workspace, size_t ws_bytes,
+                        void *stream) {
+  hh_status st;
+  if ((st = check_stack(p)) || (st = check_precision(p))) return st;
+  if (!holo || !cov) return fail(HH_E_INVALID, "holo and cov must be non-NULL");
+  if (!aligned(holo, 16) || !aligned(cov, 16)) return fail(HH_E_INVALID, "holo/cov misaligned");
+  const size_t need = cov_ws_bytes(p);
+  if (!workspace || ws_bytes < need || !aligned(workspace, 256))
+    return fail(HH_E_WORKSPACE, "covariance workspace: need %zu bytes (256-byte aligned), got %zu", need, ws_bytes);
+  const long long npix = (long long)p->nx * p->ny;
+  const GramLayout g = gram_layout(p->nt, npix);
+  char *ws = static_cast<char *>(workspace);
+  hipError_t e = launch_gram(g, reinterpret_cast<const float2 *>(holo), p->nt, npix, reinterpret_cast<double *>(ws),
+                             reinterpret_cast<double *>(ws + align_up(g.partial_bytes)), cov, (hipStream_t)stream);
+  if (e != hipSuccess) return device_fail(e, "hh_covariance");
+  return HH_OK;
+}
+
+hh_status hh_eigh_ex(int32_t nt, const double *cov, double *evals, double *evecs, int32_t *info, int32_t max_sweeps,
+                     void *stream) {
+  if (nt < 2 || nt > 64) return fail(HH_E_UNSUPPORTED, "nt=%d: must be in [2, 64]", nt);
+  if (!cov || !evals || !evecs || !info) return fail(HH_E_INVALID, "cov, evals, evecs, info must be non-NULL");
+  if (!aligned(cov, 16) || !aligned(evecs, 16) || !aligned(evals, 8) || !aligned(info, 4))
+    return fail(HH_E_INVALID, "eigh arrays misaligned");
+  if (max_sweeps < 0) return fail(HH_E_INVALID, "max_sweeps must be >= 0");
+  hipError_t e = launch_eigh(nt, cov, evals, evecs, info, max_sweeps, (hipStream_t)stream);
+  if (e != hipSuccess) return device_fail(e, "hh_eigh");
+  return HH_OK;
+}
+
+hh_status hh_eigh(int32_t nt, const double *cov, double *evals, double *evecs, int32_t *info, void *stream) {
+  return hh_eigh_ex(nt, cov, evals, evecs, info, 40, stream);
+}
+
+hh_status hh_project_render(const hh_params *p, const float *holo, const double *evecs, float *image, void *stream) {
+  hh_status st;
+  if ((st = check_stack(p)) || (st = check_select(p)) || (st = check_precision(p))) return st;
+  if (!holo || !evecs || !image) return fail(HH_E_INVALID, "holo, evecs, image must be non-NULL");
+  if (!aligned(holo, 16) || !aligned(evecs, 16) || !aligned(image, 8))
+    return fail(HH_E_INVALID, "holo/evecs/image misaligned");
+  hipError_t e = launch_project(reinterpret_cast<const float2 *>(holo), p->nt, (long long)p->nx * p->ny, evecs,
+                                p->k_lo, p->k_hi, p->proj_mode, image, (hipStream_t)stream);
+  if (e != hipSuccess) return device_fail(e, "hh_project_render");
+  return HH_OK;
+}
+
+hh_status hh_fourier_render(const hh_params *p, const float *holo, float *image, void *stream) {
+  hh_status st;
+  if ((st = check_stack(p)) || (st = check_select(p))) return st;
+  if (!holo || !image) return fail(HH_E_INVALID, "holo, image must be non-NULL");
+  if (!aligned(holo, 16) || !aligned(image, 8)) return fail(HH_E_INVALID, "holo/image misaligned");
+  const double *W = get_dft_basis(p->nt);
+  if (!W) return fail(HH_E_DEVICE, "DFT basis upload failed");
+  hipError_t e = launch_project(reinterpret_cast<const float2 *>(holo), p->nt, (long long)p->nx * p->ny, W, p->k_lo,
+                                p->k_hi, p->proj_mode, image, (hipStream_t)stream);
+  if (e != hipSuccess) return device_fail(e, "hh_fourier_render");
+  return HH_OK;
+}
+
+hh_status hh_pipeline(const hh_params *p, const uint16_t *frames, float *image, double *evals, double *evecs,
+                      int32_t *info, void *workspace, size_t ws_bytes, void *stream) {
+  hh_status st;
+  if ((st = check_optics(p)) || (st = check_stack(p)) || (st = check_select(p)) || (st = check_precision(p)))
+    return st;
+  if (!frames || !image) return fail(HH_E_INVALID, "frames and image must be non-NULL");
+  if (!aligned(frames, 2) || !aligned(image, 8) || (evals && !aligned(evals, 8)) || (evecs && !aligned(evecs, 16)) ||
+      (info && !aligned(info, 4)))
+    return fail(HH_E_INVALID, "pipeline arrays misaligned");
+  const PipeLayout L = pipe_layout(p);
+  if (!workspace || ws_bytes < L.total || !aligned(workspace, 256))
+    return fail(HH_E_WORKSPACE, "pipeline workspace: need %zu bytes (256-byte aligned), got %zu", L.total, ws_bytes);
+  const Plan *pl = get_plan(*p);
+  if (!pl) return HH_E_DEVICE;
+  char *ws = static_cast<char *>(workspace);
+  float2 *H = reinterpret_cast<float2 *>(ws + L.holo);
+  double *cov = reinterpret_cast<double *>(ws + L.cov);
+  double *ev = evals ? evals : reinterpret_cast<double *>(ws + L.evals);
+  double *V = evecs ? evecs : reinterpret_cast<double *>(ws + L.evecs);
+  int *inf = info ? info : reinterpret_cast<int *>(ws + L.info);
+  const long long npix = (long long)p->nx * p->ny;
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e = launch_fresnel(*pl, frames, p->nt, H, s);
+  if (e == hipSuccess)
+    e = launch_gram(L.g, H, p->nt, npix, reinterpret_cast<double *>(ws + L.part),
+                    reinterpret_cast<double *>(ws + L.part2), cov, s);
+  if (e == hipSuccess) e = launch_eigh(p->nt, cov, ev, V, inf, 40, s);
+  if (e == hipSuccess) e = launch_project(H, p->nt, npix, V, p->k_lo, p->k_hi, p->proj_mode, image, s);
+  if (e != hipSuccess) return device_fail(e, "hh_pipeline");
+  return HH_OK;
+}
+
+void hh_plan_cache_clear(void) {
+  std::lock_guard<std::mutex> g(g_plan_mu);
+  for (auto &kv : g_plans) {
+    (void)hipFree(kv.second.chirp_x);
+    (void)hipFree(kv.second.chirp_y);
+    (void)hipFree(kv.second.tw_x);
+    (void)hipFree(kv.second.tw_y);
+  }
+  g_plans.clear();
+  for (auto &kv : g_dft) (void)hipFree(kv.second);
+  g_dft.clear();
+}
+
+void hh_profile_enable(int32_t on) {
+  std::lock_guard<std::mutex> g(g_prof_mu);
+  g_prof_on = on != 0;
+}
+
+void hh_profile_reset(void) {
+  std::lock_guard<std::mutex> g(g_prof_mu);
+  for (auto &r : g_prof) {
+    (void)hipEventSynchronize(r.b);
+    g_prof_pool.push_back(r.a);
+    g_prof_pool.push_back(r.b);
+  }
+  g_prof.clear();
+}
+
+int32_t hh_profile_read(char *buf, int32_t len) {
+  std::lock_guard<std::mutex> g(g_prof_mu);
+  std::map<std::string, std::pair<long long, double>> agg;
+  for (auto &r : g_prof) {
+    float ms = 0.f;
+    if (hipEventSynchronize(r.b) == hipSuccess && hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
+      auto &x = agg[r.name];
+      x.first += 1;
+      x.second += ms;
+    }
+  }
+  std::string out = "{";
+  bool first = true;
+  for (auto &kv : agg) {
+    char tmp[256];
+    snprintf(tmp, sizeof tmp, "%s\"%s\": [%lld, %.9g]", first ? "" : ", ", kv.first.c_str(), kv.second.first,
+             kv.second.second);
+    out += tmp;
+    first = false;
+  }
+  out += "}";
+  if (buf && len > 0) {
+    const size_t n = out.size() < (size_t)(len - 1) ? out.size() : (size_t)(len - 1);
+    memcpy(buf, out.data(), n);
+    buf[n] = 0;
+  }
+  return (int32_t)out.size() + 1;
+}
+
+}  // extern "C"

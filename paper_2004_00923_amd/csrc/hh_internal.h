@@ -1,0 +1,71 @@
+// Internal declarations shared by the HIP translation units of libhh.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+
+#include "../../include/hh.h"
+
+namespace hh {
+
+// Device tables for one optical/shape configuration (owned by the plan cache).
+struct Plan {
+  int device = -1;
+  int nx = 0, ny = 0;
+  float2 *chirp_x = nullptr;  // [nx]  exp(-i alpha (m - nx/2)^2)
+  float2 *chirp_y = nullptr;  // [ny]  exp(-i alpha (n - ny/2)^2)
+  float2 *tw_x = nullptr;     // [nx]  exp(-2 pi i j / nx)
+  float2 *tw_y = nullptr;     // [ny]  exp(-2 pi i j / ny)
+};
+
+// Returns nullptr and sets the error text on failure.
+const Plan *get_plan(const hh_params &p);
+// Unitary DFT basis W[t][f] (complex128, nt x nt) on the current device, cached.
+const double *get_dft_basis(int nt);
+
+void set_error(const char *fmt, ...);
+
+// Kernel launch bracket used by the optional profiler.
+struct ProfScope {
+  const char *name;
+  hipStream_t stream;
+  void *ev0 = nullptr;
+  ProfScope(const char *n, hipStream_t s);
+  ~ProfScope();
+};
+
+// ---- launchers (each returns hipSuccess or the launch error) ----
+
+// Step (a): row pass (uint16 -> chirp -> row FFT) then in-place column FFT.
+hipError_t launch_fresnel(const Plan &pl, const uint16_t *frames, int nframes, float2 *holo,
+                          hipStream_t s);
+
+// Step (b): split-K Gram partials, fixed-order reduction, Hermitian assembly.
+struct GramLayout {
+  int nb = 1;              // 32-frame blocks (1 or 2)
+  int D = 32;              // 32 * nb
+  long long chunks = 0;    // pixel chunks of kGramChunk pixels
+  int groups = 0;          // workgroups of the partial kernel
+  int groups2 = 0;         // second-level partial count
+  size_t partial_bytes = 0, partial2_bytes = 0;
+};
+constexpr int kGramChunk = 128;       // pixels per LDS tile
+constexpr int kGramChunksPerWG = 16;  // tiles per workgroup (FP32 sums <= 512 px per lane)
+GramLayout gram_layout(int nt, long long npix);
+hipError_t launch_gram(const GramLayout &L, const float2 *holo, int nt, long long npix,
+                       double *partial, double *partial2, double *cov, hipStream_t s);
+
+// Step (c)
+hipError_t launch_eigh(int nt, const double *cov, double *evals, double *evecs, int *info,
+                       int max_sweeps, hipStream_t s);
+
+// Steps (d)+(e)
+hipError_t launch_project(const float2 *holo, int nt, long long npix, const double *V, int k_lo,
+                          int k_hi, int mode, float *image, hipStream_t s);
+
+inline size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
+
+}  // namespace hh

@@ -1,0 +1,231 @@
+"""Thin Python binding of libhh (ctypes): argument marshalling only.
+
+Every step of the hot path runs in the HIP kernels of libhh.so; this module
+checks tensor shapes/dtypes/devices, passes raw device pointers and the current
+torch stream, and turns status codes into exceptions.  PyTorch provides device
+memory and streams, nothing else.  There is no CPU fallback: if the library is
+missing, loading fails loudly.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libhh.so")
+
+HH_OK, HH_E_INVALID, HH_E_UNSUPPORTED, HH_E_WORKSPACE, HH_E_DEVICE, HH_E_NOT_CONVERGED = range(6)
+HH_FP32, HH_BF16, HH_FP16, HH_BF16X3, HH_FP16X3, HH_FP8E4M3 = range(6)
+HH_PROJ_AUTO, HH_PROJ_DIRECT, HH_PROJ_COMPLEMENT = range(3)
+
+PRECISIONS = {"fp32": HH_FP32, "bf16": HH_BF16, "fp16": HH_FP16, "bf16x3": HH_BF16X3,
+              "fp16x3": HH_FP16X3, "fp8e4m3": HH_FP8E4M3}
+
+
+class hh_params(ctypes.Structure):
+    _fields_ = [
+        ("wavelength_m", ctypes.c_double),
+        ("distance_m", ctypes.c_double),
+        ("pitch_m", ctypes.c_double),
+        ("nx", ctypes.c_int32),
+        ("ny", ctypes.c_int32),
+        ("nt", ctypes.c_int32),
+        ("k_lo", ctypes.c_int32),
+        ("k_hi", ctypes.c_int32),
+        ("precision", ctypes.c_int32),
+        ("proj_mode", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+    ]
+
+
+@dataclass
+class Params:
+    """Problem statement of one stack: optics, shape, kept components, arithmetic."""
+    nx: int
+    ny: int
+    nt: int
+    k_lo: int
+    k_hi: int
+    wavelength_m: float = 785e-9
+    distance_m: float = 0.3
+    pitch_m: float = 20e-6
+    precision: int = HH_FP32
+    proj_mode: int = HH_PROJ_AUTO
+
+    def c(self) -> hh_params:
+        return hh_params(self.wavelength_m, self.distance_m, self.pitch_m, self.nx, self.ny, self.nt,
+                         self.k_lo, self.k_hi, self.precision, self.proj_mode, 0)
+
+
+class HHError(RuntimeError):
+    def __init__(self, status: int, detail: str):
+        super().__init__(f"hh status {status}: {detail}")
+        self.status = status
+
+
+_lib = None
+_P = ctypes.c_void_p
+
+# name -> (restype, argtypes); mirrors include/hh.h
+SIGNATURES = {
+    "hh_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(hh_params)]),
+    "hh_covariance_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(hh_params)]),
+    "hh_fresnel": (ctypes.c_int32, [ctypes.POINTER(hh_params), _P, ctypes.c_int32, _P, _P]),
+    "hh_covariance": (ctypes.c_int32, [ctypes.POINTER(hh_params), _P, _P, _P, ctypes.c_size_t, _P]),
+    "hh_eigh": (ctypes.c_int32, [ctypes.c_int32, _P, _P, _P, _P, _P]),
+    "hh_eigh_ex": (ctypes.c_int32, [ctypes.c_int32, _P, _P, _P, _P, ctypes.c_int32, _P]),
+    "hh_project_render": (ctypes.c_int32, [ctypes.POINTER(hh_params), _P, _P, _P, _P]),
+    "hh_pipeline": (ctypes.c_int32, [ctypes.POINTER(hh_params), _P, _P, _P, _P, _P, _P, ctypes.c_size_t, _P]),
+    "hh_fourier_render": (ctypes.c_int32, [ctypes.POINTER(hh_params), _P, _P, _P]),
+    "hh_status_string": (ctypes.c_char_p, [ctypes.c_int32]),
+    "hh_last_error": (ctypes.c_char_p, []),
+    "hh_plan_cache_clear": (None, []),
+    "hh_profile_enable": (None, [ctypes.c_int32]),
+    "hh_profile_read": (ctypes.c_int32, [ctypes.c_char_p, ctypes.c_int32]),
+    "hh_profile_reset": (None, []),
+}
+
+
+def lib() -> ctypes.CDLL:
+    """Load libhh.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                              "(python -c 'import __graft_entry__ as g; g.build()')")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(status: int):
+    if status != HH_OK:
+        raise HHError(status, lib().hh_last_error().decode())
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _stream(stream):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _dev_tensor(t, dtype, shape, name):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise ValueError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+
+
+def workspace_bytes(p: Params) -> int:
+    return int(lib().hh_workspace_bytes(ctypes.byref(p.c())))
+
+
+def covariance_workspace_bytes(p: Params) -> int:
+    return int(lib().hh_covariance_workspace_bytes(ctypes.byref(p.c())))
+
+
+def hh_fresnel(p: Params, frames, holo, stream=None):
+    """Step (a): frames uint16 [n, ny, nx] -> holo complex64 [n, ny, nx]."""
+    import torch
+    n = frames.shape[0]
+    _dev_tensor(frames, torch.uint16, (n, p.ny, p.nx), "frames")
+    _dev_tensor(holo, torch.complex64, (n, p.ny, p.nx), "holo")
+    _check(lib().hh_fresnel(ctypes.byref(p.c()), _ptr(frames), n, _ptr(holo), _stream(stream)))
+    return holo
+
+
+def hh_covariance(p: Params, holo, cov, workspace, stream=None):
+    """Step (b): holo complex64 [nt, ny, nx] -> cov complex128 [nt, nt]."""
+    import torch
+    _dev_tensor(holo, torch.complex64, (p.nt, p.ny, p.nx), "holo")
+    _dev_tensor(cov, torch.complex128, (p.nt, p.nt), "cov")
+    _check(lib().hh_covariance(ctypes.byref(p.c()), _ptr(holo), _ptr(cov), _ptr(workspace),
+                               workspace.numel() * workspace.element_size(), _stream(stream)))
+    return cov
+
+
+def hh_eigh(nt: int, cov, evals, evecs, info, max_sweeps=None, stream=None):
+    """Step (c): cov complex128 [nt, nt] -> evals float64 [nt] (descending),
+    evecs complex128 [nt, nt] (column k = eigenvector k), info int32 [1]."""
+    import torch
+    _dev_tensor(cov, torch.complex128, (nt, nt), "cov")
+    _dev_tensor(evals, torch.float64, (nt,), "evals")
+    _dev_tensor(evecs, torch.complex128, (nt, nt), "evecs")
+    _dev_tensor(info, torch.int32, (1,), "info")
+    if max_sweeps is None:
+        st = lib().hh_eigh(nt, _ptr(cov), _ptr(evals), _ptr(evecs), _ptr(info), _stream(stream))
+    else:
+        st = lib().hh_eigh_ex(nt, _ptr(cov), _ptr(evals), _ptr(evecs), _ptr(info), int(max_sweeps),
+                              _stream(stream))
+    _check(st)
+
+
+def hh_project_render(p: Params, holo, evecs, image, stream=None):
+    """Steps (d)+(e): holo complex64 [nt, ny, nx], evecs complex128 [nt, nt] -> image float32 [ny, nx]."""
+    import torch
+    _dev_tensor(holo, torch.complex64, (p.nt, p.ny, p.nx), "holo")
+    _dev_tensor(evecs, torch.complex128, (p.nt, p.nt), "evecs")
+    _dev_tensor(image, torch.float32, (p.ny, p.nx), "image")
+    _check(lib().hh_project_render(ctypes.byref(p.c()), _ptr(holo), _ptr(evecs), _ptr(image), _stream(stream)))
+    return image
+
+
+def hh_fourier_render(p: Params, holo, image, stream=None):
+    """Eqs. (8)-(9): temporal-DFT band k_lo..k_hi power image."""
+    import torch
+    _dev_tensor(holo, torch.complex64, (p.nt, p.ny, p.nx), "holo")
+    _dev_tensor(image, torch.float32, (p.ny, p.nx), "image")
+    _check(lib().hh_fourier_render(ctypes.byref(p.c()), _ptr(holo), _ptr(image), _stream(stream)))
+    return image
+
+
+def hh_pipeline(p: Params, frames, image, workspace, evals=None, evecs=None, info=None, stream=None):
+    """Steps (a)-(e): frames uint16 [nt, ny, nx] -> image float32 [ny, nx]."""
+    import torch
+    _dev_tensor(frames, torch.uint16, (p.nt, p.ny, p.nx), "frames")
+    _dev_tensor(image, torch.float32, (p.ny, p.nx), "image")
+    if evals is not None:
+        _dev_tensor(evals, torch.float64, (p.nt,), "evals")
+    if evecs is not None:
+        _dev_tensor(evecs, torch.complex128, (p.nt, p.nt), "evecs")
+    if info is not None:
+        _dev_tensor(info, torch.int32, (1,), "info")
+    _check(lib().hh_pipeline(ctypes.byref(p.c()), _ptr(frames), _ptr(image), _ptr(evals), _ptr(evecs),
+                             _ptr(info), _ptr(workspace), workspace.numel() * workspace.element_size(),
+                             _stream(stream)))
+    return image
+
+
+def alloc_workspace(nbytes: int, device="cuda"):
+    import torch
+    return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device)
+
+
+def profile_enable(on: bool = True):
+    lib().hh_profile_enable(1 if on else 0)
+
+
+def profile_reset():
+    lib().hh_profile_reset()
+
+
+def profile_read() -> dict:
+    import json
+    n = lib().hh_profile_read(None, 0)
+    buf = ctypes.create_string_buffer(n)
+    lib().hh_profile_read(buf, n)
+    return {k: (int(v[0]), float(v[1])) for k, v in json.loads(buf.value.decode()).items()}

@@ -1,0 +1,123 @@
+"""The C-ABI library loads, exports every declared symbol, and validates on the
+host (no device work is done by any call in this file)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_2004_00923_amd.hh as hh
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "hh.h")
+
+
+def declared_symbols():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(hh_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = hh.lib()
+    names = declared_symbols()
+    assert len(names) >= 14
+    for n in names:
+        assert hasattr(L, n), f"{n} declared in include/hh.h but not exported"
+    assert set(names) == set(hh.SIGNATURES), "binding signatures out of sync with include/hh.h"
+
+
+def test_params_struct_layout():
+    # 3 doubles + 8 int32, no padding: the C struct is 56 bytes
+    assert ctypes.sizeof(hh.hh_params) == 56
+    src = open(HEADER).read()
+    for f, _ in hh.hh_params._fields_:
+        assert re.search(rf"\b{f}\b", src), f
+
+
+def _call_fresnel(p, nframes=1):
+    return hh.lib().hh_fresnel(ctypes.byref(p), ctypes.c_void_p(16), nframes, ctypes.c_void_p(16), None)
+
+
+def good():
+    return hh.Params(nx=1024, ny=1024, nt=32, k_lo=2, k_hi=31).c()
+
+
+@pytest.mark.parametrize("field,value,status", [
+    ("nx", 1000, hh.HH_E_UNSUPPORTED), ("ny", 4, hh.HH_E_UNSUPPORTED), ("nx", 8192, hh.HH_E_UNSUPPORTED),
+    ("nx", 0, hh.HH_E_INVALID), ("wavelength_m", 0.0, hh.HH_E_INVALID), ("wavelength_m", float("nan"), hh.HH_E_INVALID),
+    ("distance_m", 0.0, hh.HH_E_INVALID), ("pitch_m", -1.0, hh.HH_E_INVALID), ("reserved", 1, hh.HH_E_INVALID),
+])
+def test_fresnel_rejects_bad_params(field, value, status):
+    p = good()
+    setattr(p, field, value)
+    assert _call_fresnel(p) == status
+    assert hh.lib().hh_last_error().decode() != ""
+
+
+def test_null_and_counts():
+    L = hh.lib()
+    p = good()
+    assert L.hh_fresnel(ctypes.byref(p), None, 1, ctypes.c_void_p(16), None) == hh.HH_E_INVALID
+    assert L.hh_fresnel(None, ctypes.c_void_p(16), 1, ctypes.c_void_p(16), None) == hh.HH_E_INVALID
+    assert _call_fresnel(p, -1) == hh.HH_E_INVALID
+    assert _call_fresnel(p, 0) == hh.HH_OK          # empty stack: nothing to do
+    assert L.hh_fresnel(ctypes.byref(p), ctypes.c_void_p(16), 1, ctypes.c_void_p(12), None) == hh.HH_E_INVALID
+
+
+@pytest.mark.parametrize("k_lo,k_hi,nt,status", [
+    (2, 31, 32, hh.HH_OK), (0, 0, 2, hh.HH_OK), (3, 2, 32, hh.HH_E_INVALID), (-1, 5, 32, hh.HH_E_INVALID),
+    (0, 32, 32, hh.HH_E_INVALID), (0, 0, 1, hh.HH_E_UNSUPPORTED), (0, 64, 65, hh.HH_E_UNSUPPORTED),
+])
+def test_selection_validation(k_lo, k_hi, nt, status):
+    p = hh.Params(nx=64, ny=64, nt=nt, k_lo=k_lo, k_hi=k_hi).c()
+    L = hh.lib()
+    # too-small workspace makes a valid call stop at the workspace check, before any device work
+    st = L.hh_pipeline(ctypes.byref(p), ctypes.c_void_p(16), ctypes.c_void_p(16), None, None, None,
+                       ctypes.c_void_p(256), 1, None)
+    assert st == (hh.HH_E_WORKSPACE if status == hh.HH_OK else status)
+    assert (L.hh_workspace_bytes(ctypes.byref(p)) > 0) == (status == hh.HH_OK)
+
+
+def test_workspace_sizes():
+    p = hh.Params(nx=1024, ny=1024, nt=32, k_lo=2, k_hi=31)
+    ws = hh.workspace_bytes(p)
+    # the hologram stack (complex64) dominates: 32 x 1024^2 x 8 bytes
+    assert 32 * 1024 * 1024 * 8 <= ws < 32 * 1024 * 1024 * 8 * 1.1
+    cw = hh.covariance_workspace_bytes(p)
+    assert 0 < cw < 16 << 20
+    p64 = hh.Params(nx=1024, ny=1024, nt=64, k_lo=2, k_hi=63)
+    assert hh.workspace_bytes(p64) > ws
+    L = hh.lib()
+    c = p.c()
+    st = L.hh_covariance(ctypes.byref(c), ctypes.c_void_p(16), ctypes.c_void_p(16), ctypes.c_void_p(256), cw - 1, None)
+    assert st == hh.HH_E_WORKSPACE
+
+
+def test_unbuilt_precision_forms_are_reported():
+    L = hh.lib()
+    for prec in (hh.HH_BF16, hh.HH_FP16, hh.HH_BF16X3, hh.HH_FP16X3, hh.HH_FP8E4M3):
+        p = hh.Params(nx=64, ny=64, nt=8, k_lo=1, k_hi=7, precision=prec).c()
+        # a 1-byte workspace stops any call that passes the precision check before device work
+        st = L.hh_covariance(ctypes.byref(p), ctypes.c_void_p(16), ctypes.c_void_p(16), ctypes.c_void_p(256),
+                             1, None)
+        assert st in (hh.HH_E_WORKSPACE, hh.HH_E_UNSUPPORTED)
+    p = hh.Params(nx=64, ny=64, nt=8, k_lo=1, k_hi=7, precision=99).c()
+    assert L.hh_covariance(ctypes.byref(p), ctypes.c_void_p(16), ctypes.c_void_p(16), ctypes.c_void_p(256),
+                           1, None) == hh.HH_E_INVALID
+
+
+def test_eigh_validation():
+    L = hh.lib()
+    v = ctypes.c_void_p(256)
+    assert L.hh_eigh(1, v, v, v, v, None) == hh.HH_E_UNSUPPORTED
+    assert L.hh_eigh(65, v, v, v, v, None) == hh.HH_E_UNSUPPORTED
+    assert L.hh_eigh(32, None, v, v, v, None) == hh.HH_E_INVALID
+    assert L.hh_eigh_ex(32, v, v, v, v, -1, None) == hh.HH_E_INVALID
+
+
+def test_status_strings():
+    L = hh.lib()
+    for s in range(6):
+        assert L.hh_status_string(s).decode()
+    assert L.hh_status_string(77).decode() == "unknown status"

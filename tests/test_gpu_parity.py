@@ -1,0 +1,229 @@
+"""GPU parity: every entry point of the C ABI against the FP64 oracle, on the
+same seeded inputs, element by element, at sizes that span several tiles and
+the tails; plus the full 1024 x 1024 x 32 configuration."""
+import numpy as np
+import pytest
+
+import oracle
+from gpu_util import LAM, PITCH, Z, rel, say, to_dev, to_np
+from paper_2004_00923_amd.synth import gen_stack
+
+pytestmark = pytest.mark.gpu
+
+H_TOL = 2e-6      # FP32 holograms, normwise per frame
+C_TOL = 2e-6      # covariance from FP32 holograms, normwise
+IMG_TOL = 1e-5    # FP32 images, normwise (the stated bar)
+
+
+@pytest.fixture(scope="module")
+def hh():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    import paper_2004_00923_amd.hh as hh_mod
+    hh_mod.lib()
+    return hh_mod
+
+
+def _frames(seed, nt, ny, nx):
+    rng = np.random.default_rng(seed)
+    return rng.integers(0, 4096, size=(nt, ny, nx)).astype(np.uint16)
+
+
+@pytest.mark.parametrize("ny,nx,nf", [(8, 8, 3), (16, 32, 2), (64, 128, 2), (128, 64, 2), (256, 512, 1),
+                                      (512, 256, 2), (1024, 1024, 2), (2048, 1024, 1), (1024, 2048, 1),
+                                      (4096, 8, 1), (8, 4096, 1)])
+def test_fresnel_parity(hh, ny, nx, nf):
+    import torch
+    say(f"fresnel {nf}x{ny}x{nx}")
+    f = _frames(ny * 7 + nx, nf, ny, nx)
+    p = hh.Params(nx=nx, ny=ny, nt=2, k_lo=0, k_hi=1)
+    holo = torch.empty((nf, ny, nx), dtype=torch.complex64, device="cuda")
+    hh.hh_fresnel(p, to_dev(f), holo)
+    H = to_np(holo)
+    R = oracle.fresnel_ref(f, LAM, Z, PITCH)
+    for t in range(nf):
+        e = rel(H[t], R[t])
+        assert e <= H_TOL, f"frame {t}: {e:.2e}"
+
+
+def test_fresnel_point_source_peak(hh):
+    # a bright pixel pattern: the GPU and oracle agree elementwise on the peak and on its magnitude
+    import torch
+    n = 256
+    f = np.full((1, n, n), 100, dtype=np.uint16)
+    f[0, 100, 37] = 4000
+    p = hh.Params(nx=n, ny=n, nt=2, k_lo=0, k_hi=1)
+    holo = torch.empty((1, n, n), dtype=torch.complex64, device="cuda")
+    hh.hh_fresnel(p, to_dev(f), holo)
+    H = to_np(holo)[0]
+    R = oracle.fresnel_ref(f, LAM, Z, PITCH)[0]
+    assert np.unravel_index(np.abs(H).argmax(), H.shape) == np.unravel_index(np.abs(R).argmax(), R.shape)
+    assert rel(H, R) <= H_TOL
+
+
+@pytest.mark.parametrize("nt,ny,nx", [(2, 8, 8), (5, 16, 16), (16, 64, 32), (31, 32, 64), (32, 128, 128),
+                                      (33, 64, 64), (64, 64, 128), (32, 1024, 1024)])
+def test_covariance_parity(hh, nt, ny, nx):
+    import torch
+    say(f"covariance {nt}x{ny}x{nx}")
+    rng = np.random.default_rng(nt * 1000 + ny)
+    Hc = (rng.standard_normal((nt, ny, nx)) + 1j * rng.standard_normal((nt, ny, nx))).astype(np.complex64)
+    Hc += (3.0 + 1.0j) * rng.standard_normal((nt, 1, 1)).astype(np.complex64)  # correlated frames
+    p = hh.Params(nx=nx, ny=ny, nt=nt, k_lo=0, k_hi=nt - 1)
+    ws = hh.alloc_workspace(hh.covariance_workspace_bytes(p))
+    cov = torch.empty((nt, nt), dtype=torch.complex128, device="cuda")
+    hh.hh_covariance(p, to_dev(Hc), cov, ws)
+    C = to_np(cov)
+    R = oracle.covariance_ref(Hc.astype(np.complex128))
+    assert rel(C, R) <= C_TOL
+    assert np.array_equal(C, C.conj().T), "C must be exactly Hermitian"
+    assert np.all(np.diag(C).imag == 0)
+
+
+@pytest.mark.parametrize("n", [2, 3, 5, 8, 16, 31, 32, 33, 48, 64])
+def test_eigh_parity_random(hh, n):
+    import torch
+    say(f"eigh n={n}")
+    rng = np.random.default_rng(n)
+    X = rng.standard_normal((n, n + 3)) + 1j * rng.standard_normal((n, n + 3))
+    C = X @ X.conj().T
+    _eigh_check(hh, C)
+
+
+def _eigh_check(hh, C, sweeps_min=0):
+    import torch
+    n = C.shape[0]
+    ev = torch.empty(n, dtype=torch.float64, device="cuda")
+    V = torch.empty((n, n), dtype=torch.complex128, device="cuda")
+    info = torch.empty(1, dtype=torch.int32, device="cuda")
+    hh.hh_eigh(n, to_dev(C), ev, V, info)
+    w, Vg, inf = to_np(ev), to_np(V), int(to_np(info)[0])
+    wr, Vr = oracle.eigh_ref(C)
+    scale = max(abs(wr).max(), 1e-300)
+    assert inf >= sweeps_min, f"info={inf}"
+    assert np.all(np.diff(w) <= 0), "eigenvalues must be descending"
+    assert np.abs(w - wr).max() <= 1e-13 * scale
+    assert np.abs(Vg.conj().T @ Vg - np.eye(n)).max() <= 1e-13
+    assert np.linalg.norm(C @ Vg - Vg * w) <= 1e-13 * max(np.linalg.norm(C), 1e-300)
+    # eigenvectors of well-separated eigenvalues agree with the oracle, phase fixed the same way
+    for k in range(n):
+        gap = min([abs(wr[k] - wr[j]) for j in range(n) if j != k] + [np.inf]) / scale
+        if gap > 1e-4:
+            assert abs(1 - abs(np.vdot(Vr[:, k], Vg[:, k]))) <= 1e-10, f"mode {k}"
+            assert np.abs(Vg[:, k] - Vr[:, k]).max() <= 1e-8, f"phase of mode {k}"
+    return inf
+
+
+def test_eigh_special_cases(hh):
+    say("eigh special cases")
+    _eigh_check(hh, np.diag([3.0, 1.0, 2.0, 5.0]).astype(np.complex128))        # already diagonal
+    _eigh_check(hh, np.eye(6, dtype=np.complex128))                              # fully degenerate
+    _eigh_check(hh, np.zeros((4, 4), dtype=np.complex128))                       # zero matrix
+    u = np.arange(1, 9) + 1j * np.arange(8)[::-1]
+    _eigh_check(hh, np.outer(u, u.conj()))                                       # rank one
+    C = np.array([[2.0, 1j], [-1j, 2.0]])                                        # purely imaginary coupling
+    _eigh_check(hh, C)
+
+
+def test_eigh_nonconvergence_reported(hh):
+    import torch
+    n = 8
+    rng = np.random.default_rng(3)
+    X = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
+    C = X @ X.conj().T
+    ev = torch.empty(n, dtype=torch.float64, device="cuda")
+    V = torch.empty((n, n), dtype=torch.complex128, device="cuda")
+    info = torch.empty(1, dtype=torch.int32, device="cuda")
+    hh.hh_eigh(n, to_dev(C), ev, V, info, max_sweeps=0)
+    assert int(to_np(info)[0]) == -1
+    hh.hh_eigh(n, to_dev(C), ev, V, info, max_sweeps=1)
+    assert int(to_np(info)[0]) == -1
+    hh.hh_eigh(n, to_dev(C), ev, V, info)
+    assert 1 <= int(to_np(info)[0]) <= 40
+
+
+@pytest.mark.parametrize("mode", ["auto", "direct", "complement"])
+@pytest.mark.parametrize("nt,ny,nx,k_lo,k_hi", [(32, 128, 128, 2, 31), (32, 64, 64, 12, 31), (8, 16, 16, 0, 7),
+                                                 (8, 16, 16, 3, 3), (64, 32, 64, 2, 63), (5, 8, 8, 1, 3)])
+def test_project_parity(hh, mode, nt, ny, nx, k_lo, k_hi):
+    import torch
+    say(f"project {mode} {nt}x{ny}x{nx} {k_lo}..{k_hi}")
+    f = gen_stack(nt, nt, ny, nx)
+    H = oracle.fresnel_ref(f, LAM, Z, PITCH).astype(np.complex64)
+    lam, V = oracle.eigh_ref(oracle.covariance_ref(H.astype(np.complex128)))
+    pm = {"auto": hh.HH_PROJ_AUTO, "direct": hh.HH_PROJ_DIRECT, "complement": hh.HH_PROJ_COMPLEMENT}[mode]
+    p = hh.Params(nx=nx, ny=ny, nt=nt, k_lo=k_lo, k_hi=k_hi, proj_mode=pm)
+    img = torch.empty((ny, nx), dtype=torch.float32, device="cuda")
+    hh.hh_project_render(p, to_dev(H), to_dev(V), img)
+    M = to_np(img)
+    R = oracle.project_render_ref(H.astype(np.complex128), V, k_lo, k_hi)
+    assert rel(M, R) <= IMG_TOL
+    big = R > 1e-3 * R.max()
+    assert np.abs(M[big] - R[big]).max() / R[big].max() <= 1e-4
+
+
+def test_fourier_parity(hh):
+    import torch
+    nt, ny, nx = 32, 64, 64
+    f = gen_stack(4, nt, ny, nx)
+    H = oracle.fresnel_ref(f, LAM, Z, PITCH).astype(np.complex64)
+    for lo, hi in [(7, 23), (0, 31), (1, 1)]:
+        p = hh.Params(nx=nx, ny=ny, nt=nt, k_lo=lo, k_hi=hi)
+        img = torch.empty((ny, nx), dtype=torch.float32, device="cuda")
+        hh.hh_fourier_render(p, to_dev(H), img)
+        R = oracle.fourier_render_ref(H.astype(np.complex128), lo, hi)
+        assert rel(to_np(img), R) <= IMG_TOL, (lo, hi)
+
+
+def _pipeline(hh, frames, k_lo, k_hi):
+    import torch
+    nt, ny, nx = frames.shape
+    p = hh.Params(nx=nx, ny=ny, nt=nt, k_lo=k_lo, k_hi=k_hi)
+    ws = hh.alloc_workspace(hh.workspace_bytes(p))
+    img = torch.empty((ny, nx), dtype=torch.float32, device="cuda")
+    ev = torch.empty(nt, dtype=torch.float64, device="cuda")
+    V = torch.empty((nt, nt), dtype=torch.complex128, device="cuda")
+    info = torch.empty(1, dtype=torch.int32, device="cuda")
+    hh.hh_pipeline(p, to_dev(frames), img, ws, ev, V, info)
+    return to_np(img), to_np(ev), to_np(V), int(to_np(info)[0])
+
+
+def _pipeline_check(hh, frames, k_lo, k_hi):
+    M, w, V, info = _pipeline(hh, frames, k_lo, k_hi)
+    r = oracle.pipeline_ref(frames, LAM, Z, PITCH, k_lo, k_hi)
+    e_img = rel(M, r["image"])
+    e_lam = np.abs(w - r["evals"]).max() / r["evals"][0]
+    Pk = V[:, k_lo:k_hi + 1] @ V[:, k_lo:k_hi + 1].conj().T
+    Pr = r["evecs"][:, k_lo:k_hi + 1] @ r["evecs"][:, k_lo:k_hi + 1].conj().T
+    e_proj = np.linalg.norm(Pk - Pr, 2)
+    say(f"pipeline {frames.shape} PCs {k_lo}..{k_hi}: image {e_img:.2e} lambda {e_lam:.2e} "
+        f"projector {e_proj:.2e} sweeps {info}")
+    assert info >= 0
+    assert e_img <= IMG_TOL
+    assert e_lam <= 1e-6
+    return M, r
+
+
+def test_pipeline_small_config(hh):
+    # the 32 x 128 x 128 configuration, seed 0, components 2..31
+    _pipeline_check(hh, gen_stack(0, 32, 128, 128), 2, 31)
+
+
+@pytest.mark.parametrize("nt,ny,nx,k_lo", [(16, 64, 64, 2), (64, 32, 32, 2), (3, 8, 8, 1), (32, 64, 128, 12)])
+def test_pipeline_shapes(hh, nt, ny, nx, k_lo):
+    _pipeline_check(hh, gen_stack(nt + ny, nt, ny, nx), k_lo, nt - 1)
+
+
+def test_pipeline_paper_scale(hh):
+    # the 32 x 1024 x 1024 configuration, components 2..31 (and the clutter-free 3..31)
+    f = gen_stack(0, 32, 1024, 1024)
+    _pipeline_check(hh, f, 2, 31)
+    _pipeline_check(hh, f, 3, 31)
+
+
+def test_pipeline_workspace_and_repeat(hh):
+    # same input twice -> bit-identical output (fixed-order reductions)
+    f = gen_stack(9, 32, 64, 64)
+    a = _pipeline(hh, f, 2, 31)[0]
+    b = _pipeline(hh, f, 2, 31)[0]
+    assert np.array_equal(a, b)
