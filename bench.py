@@ -1,12 +1,15 @@
 """Throughput of the PCA holography hot path on one MI355X.
 
-Workload: one stack of 32 consecutive 1024 x 1024 uint16 interferograms per
-step (the paper-scale configuration), lambda 785 nm, pitch 20 um, z 0.3 m,
-principal components 2..31 kept, FP32 arithmetic.  A step is one hh_pipeline
-call: Fresnel FFT of every frame, covariance, Jacobi eigendecomposition,
-projection + |.|^2 image.  Inputs are seeded synthetic stacks, already resident
-in HBM; four distinct stacks are rotated so that no step reads an input that a
-previous step left in the 256 MB last-level cache.
+Workload: independent stacks of 32 consecutive 1024 x 1024 uint16
+interferograms (the paper-scale configuration), lambda 785 nm, pitch 20 um,
+z 0.3 m, principal components 2..31 kept, FP32 arithmetic.  A step is one
+hh_pipeline_batch call on B stacks (default 16; --batch 1 uses hh_pipeline on
+one stack): Fresnel FFT of every frame, covariance, Jacobi eigendecomposition
+(one launch for the whole batch), projection + |.|^2 image.  Inputs are seeded
+synthetic stacks, already resident in HBM; four distinct stacks are rotated so
+that consecutive stacks never read an input that the previous one left in the
+256 MB last-level cache.  Per-stack latency is measured separately on single
+stacks (hh_pipeline, each waited for).
 
 Prints ONE JSON line.  Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -83,6 +86,10 @@ def main():
     ap.add_argument("--steps", type=int, default=400)
     ap.add_argument("--warmup", type=int, default=40)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--batch", type=int, default=16,
+                    help="stacks per step, processed by one hh_pipeline_batch call (1 = hh_pipeline)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 256 MiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (each stack is "
@@ -97,22 +104,42 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.copy_calibration:
+        a = torch.empty(256 << 20, dtype=torch.uint8, device=dev).fill_(1)
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes": a.numel(), "copies": 5}))
+        return
     print("bench: generating 4 synthetic 32x1024x1024 stacks", file=sys.stderr, flush=True)
     host = [gen_stack(s, NT, NY, NX) for s in range(4)]
     frames = [torch.from_numpy(f).to(dev) for f in host]
     p = hh.Params(nx=NX, ny=NY, nt=NT, k_lo=K_LO, k_hi=K_HI)
-    ws = hh.alloc_workspace(hh.workspace_bytes(p), dev)
-    img = torch.empty((NY, NX), dtype=torch.float32, device=dev)
+    B = max(1, args.batch)
+    ws1 = hh.alloc_workspace(hh.workspace_bytes(p), dev)
+    img1 = torch.empty((NY, NX), dtype=torch.float32, device=dev)
     info = torch.empty(1, dtype=torch.int32, device=dev)
+    if B > 1:
+        ps = [p] * B
+        bimgs = [torch.empty((NY, NX), dtype=torch.float32, device=dev) for _ in range(B)]
+        binfo = [torch.empty(1, dtype=torch.int32, device=dev) for _ in range(B)]
+        bws = hh.alloc_workspace(hh.batch_workspace_bytes(ps), dev)
+        # stack j of step i reads input (i + j) % 4: consecutive stacks never share an input
+        batches = [hh.Batch(ps, [frames[(r + j) % 4] for j in range(B)], bimgs, bws, infos=binfo)
+                   for r in range(4)]
 
-    def step(i):
-        hh.hh_pipeline(p, frames[i % 4], img, ws, info=info)
+    def step(i, single=False):
+        if single or B == 1:
+            hh.hh_pipeline(p, frames[i % 4], img1, ws1, info=info)
+        else:
+            batches[i % 4].run()
 
     print(f"bench: warmup {args.warmup}", file=sys.stderr, flush=True)
     for i in range(args.warmup):
         step(i)
     torch.cuda.synchronize()
-    sweeps = int(info.cpu()[0])
+    sweeps = int((binfo[0] if B > 1 else info).cpu()[0])
 
     # timed region: exactly K steps, synchronised on both sides
     print(f"bench: timing {args.steps} steps", file=sys.stderr, flush=True)
@@ -123,7 +150,7 @@ def main():
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     ms_per_step = 1e3 * elapsed / args.steps
-    value = NT * args.steps / elapsed
+    value = NT * B * args.steps / elapsed
 
     # per-kernel durations from HIP events recorded around each launch, over a
     # second timed pass of the same K steps
@@ -140,9 +167,9 @@ def main():
     hh.profile_reset()
     kernels = {}
     for name, (n, total_ms) in prof.items():
-        per_step = n / args.steps
+        per_step = n / (args.steps * B)
         avg_us = 1e3 * total_ms / n
-        b = algorithmic_bytes(name, round(per_step))
+        b = algorithmic_bytes(name, max(1, round(per_step)))
         kernels[name] = {"launches_per_step": per_step, "avg_us": avg_us,
                          "share": total_ms / (1e3 * prof_elapsed) if prof_elapsed > 0 else None,
                          "gbs": (b / (avg_us * 1e-6) / 1e9) if b == b else None}
@@ -160,7 +187,7 @@ def main():
         e1 = torch.cuda.Event(enable_timing=True)
         torch.cuda.synchronize()
         e0.record()
-        step(i)
+        step(i, single=True)
         e1.record()
         torch.cuda.synchronize()
         lat.append(e0.elapsed_time(e1))
@@ -181,11 +208,12 @@ def main():
         "data": "synthetic",
         "config": {"workload": "one 32x1024x1024 uint16 stack per step (4 seeded stacks rotated), "
                                "lambda 785 nm, pitch 20 um, z 0.3 m, PCs 2..31, FP32",
-                   "stacks_per_s": value / NT, "precision": "fp32", "jacobi_sweeps": sweeps},
+                   "stacks_per_s": value / NT, "precision": "fp32", "jacobi_sweeps": sweeps,
+                   "stacks_per_step": B, "ms_per_stack": ms_per_step / B},
         "roofline": roofline,
         "stack_roofline": {"bytes_per_stack": STACK_BYTES,
-                           "achieved": STACK_BYTES / (ms_per_step * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
-                           "unit": "GB/s", "frac": STACK_BYTES / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS},
+                           "achieved": STACK_BYTES * B / (ms_per_step * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
+                           "unit": "GB/s", "frac": STACK_BYTES * B / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS},
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
         "kernels": kernels,
     }

@@ -160,6 +160,32 @@ hh_status hh_pipeline(const hh_params *p, const uint16_t *frames, float *image,
                       double *evals, double *evecs, int32_t *info,
                       void *workspace, size_t ws_bytes, void *stream);
 
+/* One stack of a batch: its input, its image and optional eigen-outputs. */
+typedef struct {
+  const uint16_t *frames; /* uint16 [nt][ny][nx] */
+  float *image;           /* float32 [ny][nx] output */
+  double *evals;          /* float64 [nt] output, or NULL */
+  double *evecs;          /* complex128 [nt][nt] output, or NULL */
+  int32_t *info;          /* int32 [1] output (Jacobi sweeps, -1 = not converged), or NULL */
+} hh_stack;
+
+/* Bytes of workspace hh_pipeline_batch needs for the n stacks described by p[0..n-1]
+   (0 if any p[i] is invalid or n < 1). */
+size_t hh_batch_workspace_bytes(const hh_params *p, int32_t n);
+
+/*
+ * Steps (a)-(e) on n independent stacks, possibly of different sizes and stack
+ * lengths (p[i] describes stack i), all on `stream`: every stack's Fresnel
+ * transform and covariance, then one launch that solves all n eigenproblems in
+ * parallel (one workgroup each), then every stack's projection and image.  Each
+ * stack's results are those hh_pipeline would produce for it alone.
+ *   p, stacks : host arrays of n entries (read during the call only).
+ *   workspace : at least hh_batch_workspace_bytes(p, n) bytes, 256-byte aligned.
+ * 1 <= n <= 4096.
+ */
+hh_status hh_pipeline_batch(const hh_params *p, int32_t n, const hh_stack *stacks, void *workspace,
+                            size_t ws_bytes, void *stream);
+
 /*
  * Fourier demodulation, Eqs. (8)-(9) (the paper's comparison method):
  *   image[p] = sum_{f=k_lo..k_hi} |sum_t H[p][t] W[t][f]|^2,

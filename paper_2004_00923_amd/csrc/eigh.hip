@@ -1,24 +1,33 @@
 // Step (c), Eq. (5): C = V Lambda V^{t*} by parallel cyclic Jacobi in FP64, one workgroup.
 //
-// Each round applies n/2 disjoint 2x2 Hermitian rotations (round-robin pairing,
-// every pair once per sweep).  For the pair (p, q) with beta = A[p][q] = |beta| e^{i phi}:
-//   theta = (A[q][q] - A[p][p]) / (2 |beta|),  t = sgn(theta) / (|theta| + sqrt(1 + theta^2)),
-//   c = 1 / sqrt(1 + t^2),  s = t c,
-//   J = [[c, s e^{i phi}], [-s e^{-i phi}, c]],  A <- J^H A J,  V <- V J,
-// which zeroes A[p][q] and moves t|beta| between the two diagonal entries.
-// Rotations are skipped when |beta| <= 1e-15 sqrt(|A[p][p] A[q][q]|); the sweep
-// loop stops when every off-diagonal entry passes that test.  The result is
-// sorted by decreasing eigenvalue and each eigenvector's phase is fixed.
+// A sweep is m-1 rounds (m = n rounded up to even) of m/2 disjoint 2x2 Hermitian
+// rotations (round-robin pairing: every index pair once per sweep).  For a pair
+// (p, q) with a = A[p][p], b = A[q][q], beta = A[p][q], g = b - a:
+//   D = sqrt(g^2 + 4 |beta|^2),  den = sqrt(2 D (D + |g|)),
+//   c = (D + |g|) / den,  J[p][q] = sgn(g) 2 beta / den,  J[q][p] = -conj(J[p][q]),
+//   J[p][p] = J[q][q] = c,   A <- J^H A J,   V <- V J,
+// which zeroes A[p][q] and moves t|beta| = sgn(g) 2 |beta|^2 / (D + |g|) from A[p][p]
+// to A[q][q] (the textbook t = sgn(theta)/(|theta| + sqrt(1 + theta^2)),
+// theta = g / (2|beta|), rewritten to need two square roots and one division).
+//
+// Work split per round: (1) every thread rotates the 2x2 blocks {p1,q1} x {p2,q2}
+// of A it owns, in place (the four outputs share the four inputs); barrier;
+// (2) wave 0 computes the next round's rotations from three entries each, with
+// hardware reciprocal / reciprocal-square-root seeds refined by Newton steps,
+// while waves 1-3 rotate V's (row, pair) entries in place; barrier.  C is scaled
+// by an exact power of two so that its Frobenius norm is O(1).
+// A rotation is skipped when |beta| <= 1e-15 sqrt(|a b|) or |beta| <= 1e-18 ||C||_F;
+// the iteration stops when every off-diagonal entry passes that test.  The result
+// is sorted by decreasing eigenvalue and each eigenvector's phase is fixed.
 #include "hh_internal.h"
 
 namespace hh {
 namespace {
 
 constexpr double kRelTol = 1e-15;
-constexpr double kTiny = 1e-300;
-constexpr int kMaxN = 64;
+constexpr double kAbsTol = 1e-18;
 constexpr int kThreads = 256;
-constexpr int kPer = kMaxN * kMaxN / kThreads;  // elements per thread per matrix
+constexpr size_t kCuLdsBytes = 160 * 1024;
 
 __device__ __forceinline__ double2 zmul(double2 a, double2 b) {
   return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
@@ -26,146 +35,309 @@ __device__ __forceinline__ double2 zmul(double2 a, double2 b) {
 __device__ __forceinline__ double2 zconj(double2 a) { return make_double2(a.x, -a.y); }
 __device__ __forceinline__ double2 zscale(double2 a, double s) { return make_double2(a.x * s, a.y * s); }
 __device__ __forceinline__ double2 zadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ double2 zsub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
 
-__global__ __launch_bounds__(kThreads) void eigh_jacobi(int n, const double2 *__restrict__ C,
-                                                        double *__restrict__ evals, double2 *__restrict__ evecs,
-                                                        int *__restrict__ info, int max_sweeps) {
+// 1/sqrt(x) and 1/x for x > 0: hardware seeds refined by two Newton steps each
+// (quadratic convergence to double precision).
+__device__ __forceinline__ double rsq64(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  const double hx = 0.5 * x;
+  y = y * fma(-hx * y, y, 1.5);
+  y = y * fma(-hx * y, y, 1.5);
+  return y;
+}
+__device__ __forceinline__ double rcp64(double x) {
+  double y = __builtin_amdgcn_rcp(x);
+  y = y * fma(-x, y, 2.0);
+  y = y * fma(-x, y, 2.0);
+  return y;
+}
+
+// Per-round rotation data, indexed by matrix index i: partner, c_i, e_i = J[partner][i],
+// the new diagonal if rotated, and the pair list.
+template <int NMAX>
+struct RoundParams {
+  int part[NMAX];
+  int rot[NMAX];
+  double c[NMAX];
+  double2 e[NMAX];
+  double d[NMAX];
+  int pl[NMAX / 2], ql[NMAX / 2];
+};
+
+// Round-robin pairing: pair k of round r among m players (p < q; q may be the dummy).
+__device__ __forceinline__ void pair_of(int r, int k, int m, int &p, int &q) {
+  if (k == 0) {
+    p = r;
+    q = m - 1;
+  } else {
+    p = (r + k) % (m - 1);
+    q = (r - k + m - 1) % (m - 1);
+  }
+  if (p > q) {
+    const int x = p;
+    p = q;
+    q = x;
+  }
+}
+
+template <int NMAX>
+__device__ __forceinline__ void set_rotation(RoundParams<NMAX> &P, int k, int p, int q, int n, double a, double b,
+                                             double2 beta, double abs2) {
+  P.pl[k] = p;
+  P.ql[k] = q;
+  if (q >= n) {  // paired with the dummy index: no rotation
+    P.part[p] = p;
+    P.rot[p] = 0;
+    P.c[p] = 1.0;
+    P.e[p] = make_double2(0.0, 0.0);
+    return;
+  }
+  P.part[p] = q;
+  P.part[q] = p;
+  const double ab2 = beta.x * beta.x + beta.y * beta.y;
+  if (ab2 > kRelTol * kRelTol * fabs(a * b) && ab2 > abs2) {
+    const double g = b - a, ag = fabs(g), sg = g >= 0.0 ? 1.0 : -1.0;
+    const double w = g * g + 4.0 * ab2;
+    const double D = w * rsq64(w);
+    const double inv = rsq64(2.0 * D * (D + ag));  // 1 / den
+    const double tab = sg * 2.0 * ab2 * rcp64(D + ag);
+    const double c = (D + ag) * inv;
+    const double2 eq = make_double2(sg * 2.0 * inv * beta.x, sg * 2.0 * inv * beta.y);  // J[p][q]
+    P.c[p] = c;
+    P.c[q] = c;
+    P.e[q] = eq;
+    P.e[p] = make_double2(-eq.x, eq.y);  // J[q][p] = -conj(J[p][q])
+    P.d[p] = a - tab;
+    P.d[q] = b + tab;
+    P.rot[p] = 1;
+    P.rot[q] = 1;
+  } else {
+    P.c[p] = 1.0;
+    P.c[q] = 1.0;
+    P.e[p] = make_double2(0.0, 0.0);
+    P.e[q] = make_double2(0.0, 0.0);
+    P.rot[p] = 0;
+    P.rot[q] = 0;
+  }
+}
+
+// One entry of J^H A J (A given by row stride ld) under the rotations in P.
+template <int NMAX>
+__device__ __forceinline__ double2 rotated_entry(const double2 *A, int ld, const RoundParams<NMAX> &P, int i, int j) {
+  const int ip = P.part[i], jp = P.part[j];
+  if (i == j) return make_double2(P.rot[i] ? P.d[i] : A[i * ld + i].x, 0.0);
+  if (j == ip && P.rot[i]) return make_double2(0.0, 0.0);
+  const double ci = P.c[i], cj = P.c[j];
+  const double2 eic = zconj(P.e[i]), ej = P.e[j];
+  double2 x = zscale(A[i * ld + j], ci * cj);
+  x = zadd(x, zmul(zscale(ej, ci), A[i * ld + jp]));
+  x = zadd(x, zmul(zscale(eic, cj), A[ip * ld + j]));
+  x = zadd(x, zmul(zmul(eic, ej), A[ip * ld + jp]));
+  return x;
+}
+
+template <int NMAX>
+__global__ __launch_bounds__(kThreads) void eigh_jacobi(EighBatch batch, int max_sweeps) {
+  // one workgroup per problem of the batch
+  const EighProblem &pr = batch.prob[blockIdx.x];
+  const int n = pr.n;
+  const double2 *__restrict__ C = reinterpret_cast<const double2 *>(pr.cov);
+  double *__restrict__ evals = pr.evals;
+  double2 *__restrict__ evecs = reinterpret_cast<double2 *>(pr.evecs);
+  int *__restrict__ info = pr.info;
+  constexpr int LD = NMAX + 1;
+  constexpr int NPMAX = NMAX / 2;
+  constexpr int NBLK = NPMAX * (NPMAX + 1) / 2;
+  constexpr int BPT = (NBLK + kThreads - 1) / kThreads;          // A blocks per thread
+  constexpr int VTH = kThreads - 64;                              // threads rotating V (waves 1..3)
+  constexpr int VPT = (NMAX * NPMAX + VTH - 1) / VTH;             // V (row, pair) items per thread
   extern __shared__ double2 smem[];
-  const int ld = n + 1;
-  double2 *A = smem;            // [n][ld]
-  double2 *V = smem + n * ld;   // [n][ld]
-  __shared__ int partner[kMaxN];
-  __shared__ int rotated[kMaxN];
-  __shared__ double cc[kMaxN];
-  __shared__ double2 ee[kMaxN];
-  __shared__ double dnew[kMaxN];
-  __shared__ int rank_of[kMaxN];
-  __shared__ int not_done;
+  double2 *const A = smem;              // [n][LD]
+  double2 *const V = smem + NMAX * LD;  // [n][LD]
+  __shared__ RoundParams<NMAX> prm[2];
+  __shared__ int flag;
+  __shared__ double red[kThreads];
+  __shared__ int rank_of[NMAX];
   const int tid = threadIdx.x;
-  const int m = n + (n & 1);  // even number of players (one dummy if n is odd)
+  const int m = n + (n & 1);
+  const int np = m / 2;
+  const int nblk = np * (np + 1) / 2;
+
+  // blocks (P <= Q) owned by this thread, unranked once
+  int bP[BPT], bQ[BPT];
+#pragma unroll
+  for (int u = 0; u < BPT; ++u) {
+    int b = tid + kThreads * u, P = 0;
+    bP[u] = -1;
+    bQ[u] = -1;
+    if (b < nblk) {
+      while (b >= np - P) {
+        b -= np - P;
+        ++P;
+      }
+      bP[u] = P;
+      bQ[u] = P + b;
+    }
+  }
+
+  // Frobenius norm -> exact power-of-two scale
+  double s2 = 0.0;
+  for (int e = tid; e < n * n; e += kThreads) {
+    const double2 v = C[e];
+    s2 += v.x * v.x + v.y * v.y;
+  }
+  red[tid] = s2;
+  __syncthreads();
+  if (tid == 0) {
+    double t = 0.0;
+    for (int k = 0; k < kThreads; ++k) t += red[k];
+    red[0] = t;
+  }
+  __syncthreads();
+  const double fro = sqrt(red[0]);
+  const double scale = fro > 0.0 ? ldexp(1.0, -ilogb(fro)) : 1.0;
+  const double abs2 = (kAbsTol * fro * scale) * (kAbsTol * fro * scale);
 
   // Hermitian input: the lower triangle and the real diagonal are read.
   for (int e = tid; e < n * n; e += kThreads) {
-    const int i = e / n, j = e % n;
+    const int i = e / n, j = e - (e / n) * n;
     double2 a;
     if (i > j) a = C[i * n + j];
     else if (i < j) a = zconj(C[j * n + i]);
     else a = make_double2(C[i * n + i].x, 0.0);
-    A[i * ld + j] = a;
-    V[i * ld + j] = make_double2(i == j ? 1.0 : 0.0, 0.0);
+    A[i * LD + j] = zscale(a, scale);
+    V[i * LD + j] = make_double2(i == j ? 1.0 : 0.0, 0.0);
   }
   __syncthreads();
 
   int sweeps = 0;
   bool converged = false;
   for (;;) {
-    // convergence test over all off-diagonal pairs
-    if (tid == 0) not_done = 0;
+    if (tid == 0) flag = 0;
     __syncthreads();
     for (int e = tid; e < n * n; e += kThreads) {
-      const int i = e / n, j = e % n;
+      const int i = e / n, j = e - (e / n) * n;
       if (i < j) {
-        const double2 b = A[i * ld + j];
-        const double ab = sqrt(b.x * b.x + b.y * b.y);
-        const double th = kRelTol * sqrt(fabs(A[i * ld + i].x * A[j * ld + j].x));
-        if (ab > th && ab > kTiny) not_done = 1;
+        const double2 b = A[i * LD + j];
+        const double ab2 = b.x * b.x + b.y * b.y;
+        if (ab2 > kRelTol * kRelTol * fabs(A[i * LD + i].x * A[j * LD + j].x) && ab2 > abs2) flag = 1;
       }
     }
     __syncthreads();
-    if (!not_done) { converged = true; break; }
+    if (!flag) {
+      converged = true;
+      break;
+    }
     if (sweeps >= max_sweeps) break;
     ++sweeps;
 
+    if (tid < np) {
+      int p, q;
+      pair_of(0, tid, m, p, q);
+      const int qc = q < n ? q : p;
+      set_rotation(prm[0], tid, p, q, n, A[p * LD + p].x, A[qc * LD + qc].x, A[p * LD + qc], abs2);
+    }
+    __syncthreads();
+
+    int pb = 0;
     for (int r = 0; r < m - 1; ++r) {
-      // (1) rotation parameters, one pair per thread
-      if (tid < m / 2) {
-        int p, q;
-        if (tid == 0) { p = r; q = m - 1; }
-        else { p = (r + tid) % (m - 1); q = (r - tid + m - 1) % (m - 1); }
-        if (p > q) { const int x = p; p = q; q = x; }
-        if (q >= n) {  // paired with the dummy player: no rotation
-          partner[p] = p; cc[p] = 1.0; ee[p] = make_double2(0.0, 0.0); rotated[p] = 0;
+      const RoundParams<NMAX> &P = prm[pb];
+      // (1) A <- J^H A J on the blocks this thread owns (in place: a block has one owner)
+#pragma unroll
+      for (int u = 0; u < BPT; ++u) {
+        if (bP[u] < 0) continue;
+        const int p1 = P.pl[bP[u]], q1 = P.ql[bP[u]], p2 = P.pl[bQ[u]], q2 = P.ql[bQ[u]];
+        if (bP[u] == bQ[u]) {
+          if (q1 < n) {
+            const double2 x = rotated_entry(A, LD, P, p1, q1);
+            const double2 dp = rotated_entry(A, LD, P, p1, p1);
+            const double2 dq = rotated_entry(A, LD, P, q1, q1);
+            A[p1 * LD + p1] = dp;
+            A[q1 * LD + q1] = dq;
+            A[p1 * LD + q1] = x;
+            A[q1 * LD + p1] = zconj(x);
+          }
         } else {
-          const double a = A[p * ld + p].x, b = A[q * ld + q].x;
-          const double2 beta = A[p * ld + q];
-          const double ab = sqrt(beta.x * beta.x + beta.y * beta.y);
-          partner[p] = q; partner[q] = p;
-          if (ab > kRelTol * sqrt(fabs(a * b)) && ab > kTiny) {
-            const double theta = (b - a) / (2.0 * ab);
-            double t;
-            if (fabs(theta) > 1e150) t = 0.5 / theta;
-            else t = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(1.0 + theta * theta));
-            const double c = 1.0 / sqrt(1.0 + t * t), s = t * c;
-            const double2 ph = make_double2(beta.x / ab, beta.y / ab);  // e^{i phi}
-            cc[p] = c; cc[q] = c;
-            ee[p] = zscale(zconj(ph), -s);  // J[q][p]
-            ee[q] = zscale(ph, s);          // J[p][q]
-            dnew[p] = a - t * ab; dnew[q] = b + t * ab;
-            rotated[p] = 1; rotated[q] = 1;
-          } else {
-            cc[p] = 1.0; cc[q] = 1.0;
-            ee[p] = make_double2(0.0, 0.0); ee[q] = make_double2(0.0, 0.0);
-            rotated[p] = 0; rotated[q] = 0;
+          const bool vq1 = q1 < n, vq2 = q2 < n;
+          // value selects (clamped indices), never a select between LDS and a local
+          const int q1c = vq1 ? q1 : p1, q2c = vq2 ? q2 : p2;
+          const double m1 = vq1 ? 1.0 : 0.0, m2 = vq2 ? 1.0 : 0.0;
+          const double2 a = A[p1 * LD + p2];
+          const double2 b = zscale(A[p1 * LD + q2c], m2);
+          const double2 d = zscale(A[q1c * LD + p2], m1);
+          const double2 f = zscale(A[q1c * LD + q2c], m1 * m2);
+          // T = M J2 (columns p2, q2), then J1^H T (rows p1, q1)
+          const double c1 = P.c[p1], c2 = P.c[p2];
+          const double2 e1 = zscale(P.e[q1c], m1);  // J[p1][q1]
+          const double2 e2 = zscale(P.e[q2c], m2);  // J[p2][q2]
+          const double2 me2c = make_double2(-e2.x, e2.y);  // J[q2][p2]
+          const double2 t00 = zadd(zscale(a, c2), zmul(b, me2c)), t01 = zadd(zmul(a, e2), zscale(b, c2));
+          const double2 t10 = zadd(zscale(d, c2), zmul(f, me2c)), t11 = zadd(zmul(d, e2), zscale(f, c2));
+          const double2 o00 = zsub(zscale(t00, c1), zmul(e1, t10));
+          const double2 o01 = zsub(zscale(t01, c1), zmul(e1, t11));
+          const double2 e1c = zconj(e1);
+          const double2 o10 = zadd(zmul(e1c, t00), zscale(t10, c1));
+          const double2 o11 = zadd(zmul(e1c, t01), zscale(t11, c1));
+          A[p1 * LD + p2] = o00;
+          A[p2 * LD + p1] = zconj(o00);
+          if (vq2) {
+            A[p1 * LD + q2] = o01;
+            A[q2 * LD + p1] = zconj(o01);
+          }
+          if (vq1) {
+            A[q1 * LD + p2] = o10;
+            A[p2 * LD + q1] = zconj(o10);
+          }
+          if (vq1 && vq2) {
+            A[q1 * LD + q2] = o11;
+            A[q2 * LD + q1] = zconj(o11);
           }
         }
       }
       __syncthreads();
-      // (2) new entries into registers: A' = J^H A J (upper triangle), V' = V J
-      double2 na[kPer], nv[kPer];
+      if (tid < 64) {
+        // (2a) wave 0: the next round's rotations from the updated A
+        if (r + 1 < m - 1 && tid < np) {
+          int p, q;
+          pair_of(r + 1, tid, m, p, q);
+          const int qc = q < n ? q : p;
+          set_rotation(prm[pb ^ 1], tid, p, q, n, A[p * LD + p].x, A[qc * LD + qc].x, A[p * LD + qc], abs2);
+        }
+      } else {
+        // (2b) waves 1..3: V <- V J, one (row, pair) item at a time, in place
 #pragma unroll
-      for (int u = 0; u < kPer; ++u) {
-        const int e = tid + kThreads * u;
-        if (e < n * n) {
-          const int i = e / n, j = e % n;
-          const int ip = partner[i], jp = partner[j];
-          const double ci = cc[i], cj = cc[j];
-          const double2 ei = ee[i], ej = ee[j];
-          if (i <= j) {
-            double2 x;
-            if (i == j) {
-              x = rotated[i] ? make_double2(dnew[i], 0.0) : make_double2(A[i * ld + i].x, 0.0);
-            } else if (j == ip && rotated[i]) {
-              x = make_double2(0.0, 0.0);
-            } else {
-              x = zscale(A[i * ld + j], ci * cj);
-              x = zadd(x, zmul(zscale(ej, ci), A[i * ld + jp]));
-              const double2 eic = zconj(ei);
-              x = zadd(x, zmul(zscale(eic, cj), A[ip * ld + j]));
-              x = zadd(x, zmul(zmul(eic, ej), A[ip * ld + jp]));
+        for (int u = 0; u < VPT; ++u) {
+          const int it = (tid - 64) + VTH * u;
+          if (it < n * np) {
+            const int row = it / np, k = it - (it / np) * np;
+            const int p = P.pl[k], q = P.ql[k];
+            if (q < n && P.rot[p]) {
+              const double2 vp = V[row * LD + p], vq = V[row * LD + q];
+              const double c = P.c[p];
+              const double2 eq = P.e[q];  // J[p][q]
+              const double2 ep = P.e[p];  // J[q][p]
+              V[row * LD + p] = zadd(zscale(vp, c), zmul(vq, ep));
+              V[row * LD + q] = zadd(zmul(vp, eq), zscale(vq, c));
             }
-            na[u] = x;
           }
-          nv[u] = zadd(zscale(V[i * ld + j], cj), zmul(V[i * ld + jp], ej));
         }
       }
       __syncthreads();
-      // (3) write back, mirroring the upper triangle
-#pragma unroll
-      for (int u = 0; u < kPer; ++u) {
-        const int e = tid + kThreads * u;
-        if (e < n * n) {
-          const int i = e / n, j = e % n;
-          if (i <= j) {
-            A[i * ld + j] = na[u];
-            if (i < j) A[j * ld + i] = zconj(na[u]);
-          }
-          V[i * ld + j] = nv[u];
-        }
-      }
-      __syncthreads();
+      pb ^= 1;
     }
   }
 
-  // sort by decreasing eigenvalue (ties: lower index first)
+  // sort by decreasing eigenvalue (ties: lower index first), undo the scale
   if (tid < n) {
-    const double di = A[tid * ld + tid].x;
+    const double di = A[tid * LD + tid].x;
     int rk = 0;
     for (int j = 0; j < n; ++j) {
-      const double dj = A[j * ld + j].x;
+      const double dj = A[j * LD + j].x;
       rk += (dj > di) || (dj == di && j < tid);
     }
     rank_of[tid] = rk;
-    evals[rk] = di;
+    evals[rk] = di / scale;
   }
   __syncthreads();
   // phase fix: the lowest row whose modulus is within 1e-12 of the largest becomes real > 0
@@ -173,44 +345,78 @@ __global__ __launch_bounds__(kThreads) void eigh_jacobi(int n, const double2 *__
     const int k = tid, col = rank_of[k];
     double mx = 0.0;
     for (int j = 0; j < n; ++j) {
-      const double2 v = V[j * ld + k];
+      const double2 v = V[j * LD + k];
       mx = fmax(mx, sqrt(v.x * v.x + v.y * v.y));
     }
     int js = 0;
     for (int j = n - 1; j >= 0; --j) {
-      const double2 v = V[j * ld + k];
+      const double2 v = V[j * LD + k];
       if (sqrt(v.x * v.x + v.y * v.y) >= mx * (1.0 - 1e-12)) js = j;
     }
-    const double2 vs = V[js * ld + k];
+    const double2 vs = V[js * LD + k];
     const double ms = sqrt(vs.x * vs.x + vs.y * vs.y);
     const double2 ph = ms > 0.0 ? make_double2(vs.x / ms, -vs.y / ms) : make_double2(1.0, 0.0);
     for (int j = 0; j < n; ++j) {
-      const double2 v = (j == js) ? make_double2(ms, 0.0) : zmul(V[j * ld + k], ph);
+      const double2 v = (j == js) ? make_double2(ms, 0.0) : zmul(V[j * LD + k], ph);
       evecs[j * n + col] = v;
     }
   }
   if (tid == 0) *info = converged ? sweeps : -1;
 }
 
-}  // namespace
+template <int NMAX>
+constexpr size_t eigh_static_lds() {
+  return 2 * sizeof(RoundParams<NMAX>) + sizeof(int) + kThreads * sizeof(double) + NMAX * sizeof(int) + 512;
+}
 
-hipError_t launch_eigh(int nt, const double *cov, double *evals, double *evecs, int *info, int max_sweeps,
-                       hipStream_t s) {
-  const size_t shmem = 2 * (size_t)nt * (nt + 1) * sizeof(double2);
+template <int NMAX>
+hipError_t launch_batch(const EighBatch &b, int count, int max_sweeps, hipStream_t s) {
   static bool attr_set[64] = {};
   int dev = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return e;
+  // The whole CU's LDS is requested so that no other workgroup (all the other
+  // kernels of the path use LDS) shares the CU with this latency-bound kernel.
+  const size_t shmem = kCuLdsBytes - eigh_static_lds<NMAX>();
   if (dev < 0 || dev >= 64 || !attr_set[dev]) {
-    e = hipFuncSetAttribute((const void *)eigh_jacobi, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            2 * kMaxN * (kMaxN + 1) * (int)sizeof(double2));
+    e = hipFuncSetAttribute((const void *)eigh_jacobi<NMAX>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)shmem);
     if (e != hipSuccess) return e;
     if (dev >= 0 && dev < 64) attr_set[dev] = true;
   }
   ProfScope ps("eigh_jacobi", s);
-  hipLaunchKernelGGL(eigh_jacobi, dim3(1), dim3(kThreads), shmem, s, nt, reinterpret_cast<const double2 *>(cov),
-                     evals, reinterpret_cast<double2 *>(evecs), info, max_sweeps);
+  hipLaunchKernelGGL((eigh_jacobi<NMAX>), dim3(count), dim3(kThreads), shmem, s, b, max_sweeps);
   return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_eigh_batch(const EighProblem *probs, int count, int max_sweeps, hipStream_t s) {
+  // problems with n <= 32 and n > 32 go to the two kernel sizes, kMaxEighBatch per launch
+  for (int big = 0; big < 2; ++big) {
+    EighBatch b{};
+    int m = 0;
+    for (int i = 0; i < count; ++i) {
+      if ((probs[i].n > 32) != (big == 1)) continue;
+      b.prob[m++] = probs[i];
+      if (m == kMaxEighBatch) {
+        hipError_t e = big ? launch_batch<64>(b, m, max_sweeps, s) : launch_batch<32>(b, m, max_sweeps, s);
+        if (e != hipSuccess) return e;
+        m = 0;
+      }
+    }
+    if (m > 0) {
+      hipError_t e = big ? launch_batch<64>(b, m, max_sweeps, s) : launch_batch<32>(b, m, max_sweeps, s);
+      if (e != hipSuccess) return e;
+    }
+  }
+  return hipSuccess;
+}
+
+hipError_t launch_eigh(int nt, const double *cov, double *evals, double *evecs, int *info, int max_sweeps,
+                       hipStream_t s) {
+  EighProblem p{nt, cov, evals, evecs, info};
+  return launch_eigh_batch(&p, 1, max_sweeps, s);
 }
 
 }  // namespace hh

@@ -72,34 +72,80 @@ __device__ __forceinline__ void dft_reg(float2 (&v)[R]) {
   }
 }
 
-// Two-pass Stockham decomposition of an N-point transform over T threads with
-// E = N / T points per thread: pass 0 is one radix-E DFT per thread, pass 1 is
-// E / T radix-T DFTs per thread (twiddled by W_N^{j k}), with one LDS exchange.
+// Mixed-radix Stockham FFT of N points over T = N / E threads, E = min(16, N)
+// points per thread.  Pass p has radix R_p (E for the first passes, the
+// remaining factor for the last) and stride NS_p = R_0 ... R_{p-1}; each thread
+// does E / R_p radix-R_p DFTs in registers, twiddled by W_N^{(j mod NS_p) k N/(NS_p R_p)},
+// and the passes exchange data through LDS.  1024 = 16 * 16 * 4.
+__host__ __device__ constexpr int fft_radix(int N, int E, int p) {
+  int ns = 1, r = E < N ? E : N;
+  for (int q = 0; q < p; ++q) {
+    ns *= r;
+    r = (N / ns) < E ? (N / ns) : E;
+  }
+  return r;
+}
+__host__ __device__ constexpr int fft_ns(int N, int E, int p) {
+  int ns = 1;
+  for (int q = 0; q < p; ++q) ns *= fft_radix(N, E, q);
+  return ns;
+}
+__host__ __device__ constexpr int fft_npasses(int N, int E) {
+  int p = 0, ns = 1;
+  while (ns < N) {
+    ns *= fft_radix(N, E, p);
+    ++p;
+  }
+  return p;
+}
+// LDS slot of logical element e: one pad slot per 32 elements spreads the banks.
+__host__ __device__ constexpr int fft_pad(int e) { return e + (e >> 5); }
+
 template <int N>
-struct FftShape {
-  static constexpr int E = (N <= 32) ? N : (N == 64 ? 8 : (N <= 256 ? 16 : (N <= 1024 ? 32 : 64)));
+struct FftCfg {
+  static constexpr int E = N < 16 ? N : 16;
   static constexpr int T = N / E;
-  static constexpr int PADN = N + N / E;  // LDS complex slots per transform (1 pad per E)
-  static_assert(T <= E && E % T == 0, "bad FFT shape");
+  static constexpr int P = fft_npasses(N, E);
+  static constexpr int LDSN = fft_pad(N - 1) + 1;  // LDS slots per transform
 };
 
-// Pass 1 of the two-pass transform.  On entry v[i] holds element t + T*i of the
-// pass-0 output; on exit v[i] holds X[t + T*i] (natural order).
-template <int N>
-__device__ __forceinline__ void fft_pass1(float2 (&v)[FftShape<N>::E], int t,
-                                          const float2 *__restrict__ tw) {
-  constexpr int E = FftShape<N>::E, T = FftShape<N>::T, B = E / T;
+// Passes P.. of the transform.  On entry v[i] holds element t + T*i of the
+// sequence entering pass P; on return v[i] = X[t + T*i] (natural order).
+// slot(e) maps a logical element of this transform to its LDS slot; every
+// thread of the workgroup must call this (it contains barriers).
+template <int N, int P, class Slot>
+__device__ __forceinline__ void fft_passes(float2 (&v)[FftCfg<N>::E], int t, const float2 *__restrict__ tw,
+                                           float2 *lds, Slot slot) {
+  constexpr int E = FftCfg<N>::E, T = FftCfg<N>::T;
+  constexpr int R = fft_radix(N, E, P), NS = fft_ns(N, E, P), B = E / R;
+  constexpr bool last = (P == FftCfg<N>::P - 1);
 #pragma unroll
   for (int b = 0; b < B; ++b) {
     const int j = t + T * b;
-    float2 u[T];
+    float2 u[R];
 #pragma unroll
-    for (int k = 0; k < T; ++k) u[k] = v[b + k * B];
+    for (int k = 0; k < R; ++k) u[k] = v[b + B * k];
+    if constexpr (NS > 1) {
+      const int jm = j & (NS - 1);
 #pragma unroll
-    for (int k = 1; k < T; ++k) u[k] = cmul(u[k], tw[j * k]);
-    dft_reg<T>(u);
+      for (int k = 1; k < R; ++k) u[k] = cmul(u[k], tw[jm * k * (N / (NS * R))]);
+    }
+    dft_reg<R>(u);
+    if constexpr (last) {
 #pragma unroll
-    for (int k = 0; k < T; ++k) v[b + k * B] = u[k];
+      for (int k = 0; k < R; ++k) v[b + B * k] = u[k];
+    } else {
+      const int base = (j / NS) * NS * R + (j & (NS - 1));
+#pragma unroll
+      for (int k = 0; k < R; ++k) lds[slot(base + k * NS)] = u[k];
+    }
+  }
+  if constexpr (!last) {
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < E; ++i) v[i] = lds[slot(t + T * i)];
+    if constexpr (P + 1 < FftCfg<N>::P - 1) __syncthreads();  // reads done before the next pass writes
+    fft_passes<N, P + 1>(v, t, tw, lds, slot);
   }
 }
 

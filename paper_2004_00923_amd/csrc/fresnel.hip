@@ -3,40 +3,48 @@
 // Two kernels per frame group:
 //   fresnel_rows : uint16 load -> FP32 -> chirp a[m] b[n] -> row FFT -> complex64 out
 //   fresnel_cols : in-place column FFT on the row-transformed frames
-// Each 1D transform is a two-pass Stockham FFT: a radix-E DFT in registers per
-// thread, one LDS exchange, then radix-T DFTs with W_N twiddles from a table
-// built in FP64 on the host.
+// Each 1D transform is a mixed-radix Stockham FFT with 16 points per thread
+// (1024 = 16 * 16 * 4: one wave per 1024-point row, 128-byte coalesced uint16
+// loads), register DFTs, LDS exchanges between passes, and W_N twiddles from a
+// table built in FP64 on the host.
 #include "fft_common.h"
 #include "hh_internal.h"
 
 namespace hh {
 namespace {
 
-// Rows per workgroup: 256 threads where the LDS exchange stays near 68 KiB.
+// Rows per workgroup (256 threads where possible).
 template <int N>
 constexpr int rows_per_wg() {
-  constexpr int T = FftShape<N>::T;
-  int r = 256 / T;
-  while (r > 1 && r * FftShape<N>::PADN * 8 > 70000) r >>= 1;
-  return r;
+  constexpr int T = FftCfg<N>::T;
+  return T >= 256 ? 1 : 256 / T;
 }
 
-// Columns per workgroup (the fast-axis width of one coalesced strip).
+// Columns per workgroup: a 128-byte strip (16 complex) where the LDS allows.
 template <int N>
 constexpr int cols_per_wg() {
-  constexpr int T = FftShape<N>::T;
-  if (T == 1) return 64;
-  int w = 256 / T;
-  if (w < 16) w = 16;
-  while (w > 1 && w * FftShape<N>::PADN * 8 > 140000) w >>= 1;
+  constexpr int T = FftCfg<N>::T;
+  int w = 1024 / T;
+  if (w > 16 && T > 1) w = 256 / T > 16 ? 256 / T : 16;
+  if (T == 1) w = 256;
+  while (w > 1 && w * FftCfg<N>::LDSN * 8 > 140000) w >>= 1;
   return w;
 }
 
+struct RowSlot {
+  __device__ __forceinline__ int operator()(int e) const { return fft_pad(e); }
+};
+template <int W>
+struct ColSlot {
+  int c;
+  __device__ __forceinline__ int operator()(int e) const { return fft_pad(e) * W + c; }
+};
+
 template <int N, int ROWS>
-__global__ __launch_bounds__(ROWS *FftShape<N>::T) void fresnel_rows(
+__global__ __launch_bounds__(ROWS *FftCfg<N>::T) void fresnel_rows(
     const uint16_t *__restrict__ frames, int ny, const float2 *__restrict__ chirp_x,
     const float2 *__restrict__ chirp_y, const float2 *__restrict__ tw, float2 *__restrict__ out) {
-  constexpr int E = FftShape<N>::E, T = FftShape<N>::T;
+  constexpr int E = FftCfg<N>::E, T = FftCfg<N>::T;
   const int t = threadIdx.x % T;
   const int r = threadIdx.x / T;
   const int row = blockIdx.x * ROWS + r;
@@ -54,19 +62,11 @@ __global__ __launch_bounds__(ROWS *FftShape<N>::T) void fresnel_rows(
       v[i] = make_float2(val * c.x, val * c.y);
     }
   }
-  dft_reg<E>(v);
-  if constexpr (T > 1) {
-    __shared__ float2 lds[ROWS * FftShape<N>::PADN];
-    float2 *my = lds + r * FftShape<N>::PADN;
-#pragma unroll
-    for (int k = 0; k < E; ++k) my[t * (E + 1) + k] = v[k];
-    __syncthreads();
-#pragma unroll
-    for (int i = 0; i < E; ++i) {
-      const int e = t + T * i;
-      v[i] = my[e + e / E];
-    }
-    fft_pass1<N>(v, t, tw);
+  if constexpr (FftCfg<N>::P > 1) {
+    __shared__ float2 lds[ROWS * FftCfg<N>::LDSN];
+    fft_passes<N, 0>(v, t, tw, lds + r * FftCfg<N>::LDSN, RowSlot{});
+  } else {
+    fft_passes<N, 0>(v, t, tw, (float2 *)nullptr, RowSlot{});
   }
   if (live) {
 #pragma unroll
@@ -75,9 +75,9 @@ __global__ __launch_bounds__(ROWS *FftShape<N>::T) void fresnel_rows(
 }
 
 template <int N, int W>
-__global__ __launch_bounds__(W *FftShape<N>::T) void fresnel_cols(float2 *__restrict__ data, int nx,
-                                                                 const float2 *__restrict__ tw) {
-  constexpr int E = FftShape<N>::E, T = FftShape<N>::T;
+__global__ __launch_bounds__(W *FftCfg<N>::T) void fresnel_cols(float2 *__restrict__ data, int nx,
+                                                               const float2 *__restrict__ tw) {
+  constexpr int E = FftCfg<N>::E, T = FftCfg<N>::T;
   const int c = threadIdx.x % W;
   const int t = threadIdx.x / W;
   const int col = blockIdx.x * W + c;
@@ -87,18 +87,11 @@ __global__ __launch_bounds__(W *FftShape<N>::T) void fresnel_cols(float2 *__rest
   float2 v[E];
 #pragma unroll
   for (int i = 0; i < E; ++i) v[i] = live ? base[(size_t)(t + T * i) * nx] : make_float2(0.f, 0.f);
-  dft_reg<E>(v);
-  if constexpr (T > 1) {
-    __shared__ float2 lds[W * FftShape<N>::PADN];
-#pragma unroll
-    for (int k = 0; k < E; ++k) lds[(t * (E + 1) + k) * W + c] = v[k];
-    __syncthreads();
-#pragma unroll
-    for (int i = 0; i < E; ++i) {
-      const int e = t + T * i;
-      v[i] = lds[(e + e / E) * W + c];
-    }
-    fft_pass1<N>(v, t, tw);
+  if constexpr (FftCfg<N>::P > 1) {
+    __shared__ float2 lds[W * FftCfg<N>::LDSN];
+    fft_passes<N, 0>(v, t, tw, lds, ColSlot<W>{c});
+  } else {
+    fft_passes<N, 0>(v, t, tw, (float2 *)nullptr, ColSlot<W>{c});
   }
   if (live) {
 #pragma unroll
@@ -111,7 +104,7 @@ hipError_t rows_n(const Plan &pl, const uint16_t *frames, int nframes, float2 *o
   constexpr int R = rows_per_wg<N>();
   dim3 grid((pl.ny + R - 1) / R, nframes);
   ProfScope ps("fresnel_rows", s);
-  hipLaunchKernelGGL((fresnel_rows<N, R>), grid, dim3(R * FftShape<N>::T), 0, s, frames, pl.ny,
+  hipLaunchKernelGGL((fresnel_rows<N, R>), grid, dim3(R * FftCfg<N>::T), 0, s, frames, pl.ny,
                      pl.chirp_x, pl.chirp_y, pl.tw_x, out);
   return hipGetLastError();
 }
@@ -121,7 +114,7 @@ hipError_t cols_n(const Plan &pl, int nframes, float2 *data, hipStream_t s) {
   constexpr int W = cols_per_wg<N>();
   dim3 grid((pl.nx + W - 1) / W, nframes);
   ProfScope ps("fresnel_cols", s);
-  hipLaunchKernelGGL((fresnel_cols<N, W>), grid, dim3(W * FftShape<N>::T), 0, s, data, pl.nx, pl.tw_y);
+  hipLaunchKernelGGL((fresnel_cols<N, W>), grid, dim3(W * FftCfg<N>::T), 0, s, data, pl.nx, pl.tw_y);
   return hipGetLastError();
 }
 

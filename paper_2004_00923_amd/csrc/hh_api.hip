@@ -378,6 +378,70 @@ hh_status hh_pipeline(const hh_params *p, const uint16_t *frames, float *image, 
   return HH_OK;
 }
 
+size_t hh_batch_workspace_bytes(const hh_params *p, int32_t n) {
+  if (!p || n < 1 || n > 4096) return 0;
+  size_t total = 0;
+  for (int i = 0; i < n; ++i) {
+    if (check_optics(p + i) || check_stack(p + i) || check_select(p + i)) return 0;
+    total += align_up(pipe_layout(p + i).total);
+  }
+  return total;
+}
+
+hh_status hh_pipeline_batch(const hh_params *p, int32_t n, const hh_stack *stacks, void *workspace,
+                            size_t ws_bytes, void *stream) {
+  if (!p || !stacks) return fail(HH_E_INVALID, "params and stacks must be non-NULL");
+  if (n < 1 || n > 4096) return fail(HH_E_INVALID, "batch size n=%d must be in [1, 4096]", n);
+  size_t need = 0;
+  for (int i = 0; i < n; ++i) {
+    hh_status st;
+    if ((st = check_optics(p + i)) || (st = check_stack(p + i)) || (st = check_select(p + i)) ||
+        (st = check_precision(p + i))) {
+      const std::string msg = g_err;
+      return fail(st, "stack %d: %s", i, msg.c_str());
+    }
+    const hh_stack &sk = stacks[i];
+    if (!sk.frames || !sk.image) return fail(HH_E_INVALID, "stack %d: frames and image must be non-NULL", i);
+    if (!aligned(sk.frames, 2) || !aligned(sk.image, 8) || (sk.evals && !aligned(sk.evals, 8)) ||
+        (sk.evecs && !aligned(sk.evecs, 16)) || (sk.info && !aligned(sk.info, 4)))
+      return fail(HH_E_INVALID, "stack %d: arrays misaligned", i);
+    need += align_up(pipe_layout(p + i).total);
+  }
+  if (!workspace || ws_bytes < need || !aligned(workspace, 256))
+    return fail(HH_E_WORKSPACE, "batch workspace: need %zu bytes (256-byte aligned), got %zu", need, ws_bytes);
+  std::vector<const Plan *> plans(n);
+  for (int i = 0; i < n; ++i)
+    if (!(plans[i] = get_plan(p[i]))) return HH_E_DEVICE;
+  hipStream_t s = (hipStream_t)stream;
+  std::vector<EighProblem> probs(n);
+  std::vector<char *> base(n);
+  char *ws = static_cast<char *>(workspace);
+  hipError_t e = hipSuccess;
+  for (int i = 0; i < n && e == hipSuccess; ++i) {
+    const PipeLayout L = pipe_layout(p + i);
+    base[i] = ws;
+    const long long npix = (long long)p[i].nx * p[i].ny;
+    float2 *H = reinterpret_cast<float2 *>(ws + L.holo);
+    double *cov = reinterpret_cast<double *>(ws + L.cov);
+    e = launch_fresnel(*plans[i], stacks[i].frames, p[i].nt, H, s);
+    if (e == hipSuccess)
+      e = launch_gram(L.g, H, p[i].nt, npix, reinterpret_cast<double *>(ws + L.part),
+                      reinterpret_cast<double *>(ws + L.part2), cov, s);
+    probs[i] = EighProblem{p[i].nt, cov, stacks[i].evals ? stacks[i].evals : reinterpret_cast<double *>(ws + L.evals),
+                           stacks[i].evecs ? stacks[i].evecs : reinterpret_cast<double *>(ws + L.evecs),
+                           stacks[i].info ? stacks[i].info : reinterpret_cast<int *>(ws + L.info)};
+    ws += align_up(L.total);
+  }
+  if (e == hipSuccess) e = launch_eigh_batch(probs.data(), n, 40, s);
+  for (int i = 0; i < n && e == hipSuccess; ++i) {
+    const PipeLayout L = pipe_layout(p + i);
+    e = launch_project(reinterpret_cast<const float2 *>(base[i] + L.holo), p[i].nt, (long long)p[i].nx * p[i].ny,
+                       probs[i].evecs, p[i].k_lo, p[i].k_hi, p[i].proj_mode, stacks[i].image, s);
+  }
+  if (e != hipSuccess) return device_fail(e, "hh_pipeline_batch");
+  return HH_OK;
+}
+
 void hh_plan_cache_clear(void) {
   std::lock_guard<std::mutex> g(g_plan_mu);
   for (auto &kv : g_plans) {

@@ -47,20 +47,31 @@ hipError_t launch_fresnel(const Plan &pl, const uint16_t *frames, int nframes, f
 struct GramLayout {
   int nb = 1;              // 32-frame blocks (1 or 2)
   int D = 32;              // 32 * nb
-  long long chunks = 0;    // pixel chunks of kGramChunk pixels
+  long long chunks = 0;    // pixel chunks of kGramPxPerWave pixels (one per wave)
   int groups = 0;          // workgroups of the partial kernel
   int groups2 = 0;         // second-level partial count
   size_t partial_bytes = 0, partial2_bytes = 0;
 };
-constexpr int kGramChunk = 128;       // pixels per LDS tile
-constexpr int kGramChunksPerWG = 16;  // tiles per workgroup (FP32 sums <= 512 px per lane)
+constexpr int kGramPxPerWave = 256;  // pixels per wave (FP32 sums <= 256 px per accumulator)
 GramLayout gram_layout(int nt, long long npix);
 hipError_t launch_gram(const GramLayout &L, const float2 *holo, int nt, long long npix,
                        double *partial, double *partial2, double *cov, hipStream_t s);
 
-// Step (c)
+// Step (c): one workgroup per problem; problems are passed by value (kernel argument).
+struct EighProblem {
+  int n;
+  const double *cov;
+  double *evals;
+  double *evecs;
+  int *info;
+};
+constexpr int kMaxEighBatch = 64;
+struct EighBatch {
+  EighProblem prob[kMaxEighBatch];
+};
 hipError_t launch_eigh(int nt, const double *cov, double *evals, double *evecs, int *info,
                        int max_sweeps, hipStream_t s);
+hipError_t launch_eigh_batch(const EighProblem *probs, int count, int max_sweeps, hipStream_t s);
 
 // Steps (d)+(e)
 hipError_t launch_project(const float2 *holo, int nt, long long npix, const double *V, int k_lo,

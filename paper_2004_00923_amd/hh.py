@@ -58,6 +58,11 @@ class Params:
                          self.k_lo, self.k_hi, self.precision, self.proj_mode, 0)
 
 
+class hh_stack(ctypes.Structure):
+    _fields_ = [("frames", ctypes.c_void_p), ("image", ctypes.c_void_p), ("evals", ctypes.c_void_p),
+                ("evecs", ctypes.c_void_p), ("info", ctypes.c_void_p)]
+
+
 class HHError(RuntimeError):
     def __init__(self, status: int, detail: str):
         super().__init__(f"hh status {status}: {detail}")
@@ -78,6 +83,9 @@ SIGNATURES = {
     "hh_project_render": (ctypes.c_int32, [ctypes.POINTER(hh_params), _P, _P, _P, _P]),
     "hh_pipeline": (ctypes.c_int32, [ctypes.POINTER(hh_params), _P, _P, _P, _P, _P, _P, ctypes.c_size_t, _P]),
     "hh_fourier_render": (ctypes.c_int32, [ctypes.POINTER(hh_params), _P, _P, _P]),
+    "hh_batch_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(hh_params), ctypes.c_int32]),
+    "hh_pipeline_batch": (ctypes.c_int32, [ctypes.POINTER(hh_params), ctypes.c_int32, ctypes.POINTER(hh_stack), _P,
+                                           ctypes.c_size_t, _P]),
     "hh_status_string": (ctypes.c_char_p, [ctypes.c_int32]),
     "hh_last_error": (ctypes.c_char_p, []),
     "hh_plan_cache_clear": (None, []),
@@ -208,6 +216,50 @@ def hh_pipeline(p: Params, frames, image, workspace, evals=None, evecs=None, inf
                              _ptr(info), _ptr(workspace), workspace.numel() * workspace.element_size(),
                              _stream(stream)))
     return image
+
+
+def _param_array(ps):
+    arr = (hh_params * len(ps))()
+    for i, p in enumerate(ps):
+        arr[i] = p.c()
+    return arr
+
+
+def batch_workspace_bytes(ps) -> int:
+    return int(lib().hh_batch_workspace_bytes(_param_array(ps), len(ps)))
+
+
+class Batch:
+    """Prepared arguments of hh_pipeline_batch (built once, launched many times)."""
+
+    def __init__(self, ps, frames, images, workspace, evals=None, evecs=None, infos=None):
+        import torch
+        n = len(ps)
+        if not (len(frames) == len(images) == n):
+            raise ValueError("one frames and one image tensor per stack")
+        for i, p in enumerate(ps):
+            _dev_tensor(frames[i], torch.uint16, (p.nt, p.ny, p.nx), f"frames[{i}]")
+            _dev_tensor(images[i], torch.float32, (p.ny, p.nx), f"images[{i}]")
+        self.params = _param_array(ps)
+        self.stacks = (hh_stack * n)()
+        for i in range(n):
+            self.stacks[i] = hh_stack(frames[i].data_ptr(), images[i].data_ptr(),
+                                      evals[i].data_ptr() if evals else None,
+                                      evecs[i].data_ptr() if evecs else None,
+                                      infos[i].data_ptr() if infos else None)
+        self.n = n
+        self.keep = (frames, images, workspace, evals, evecs, infos)
+        self.ws = workspace
+
+    def run(self, stream=None):
+        _check(lib().hh_pipeline_batch(self.params, self.n, self.stacks, _ptr(self.ws),
+                                       self.ws.numel() * self.ws.element_size(), _stream(stream)))
+
+
+def hh_pipeline_batch(ps, frames, images, workspace, evals=None, evecs=None, infos=None, stream=None):
+    """Steps (a)-(e) on a batch of (possibly uneven) stacks; see include/hh.h."""
+    Batch(ps, frames, images, workspace, evals, evecs, infos).run(stream)
+    return images
 
 
 def alloc_workspace(nbytes: int, device="cuda"):

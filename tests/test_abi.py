@@ -85,7 +85,7 @@ def test_workspace_sizes():
     # the hologram stack (complex64) dominates: 32 x 1024^2 x 8 bytes
     assert 32 * 1024 * 1024 * 8 <= ws < 32 * 1024 * 1024 * 8 * 1.1
     cw = hh.covariance_workspace_bytes(p)
-    assert 0 < cw < 16 << 20
+    assert 0 < cw < 32 << 20
     p64 = hh.Params(nx=1024, ny=1024, nt=64, k_lo=2, k_hi=63)
     assert hh.workspace_bytes(p64) > ws
     L = hh.lib()

@@ -227,3 +227,45 @@ def test_pipeline_workspace_and_repeat(hh):
     a = _pipeline(hh, f, 2, 31)[0]
     b = _pipeline(hh, f, 2, 31)[0]
     assert np.array_equal(a, b)
+
+
+def test_pipeline_batch_uneven_matches_alone_and_oracle(hh):
+    # uneven batch: different frame sizes and stack lengths in one call; every
+    # stack's image must equal its alone result (same kernels, same order of
+    # reduction) and the oracle within the FP32 bar
+    import torch
+    specs = [(16, 64, 64, 2), (32, 32, 128, 2), (64, 64, 32, 3), (32, 128, 128, 2), (8, 16, 16, 1)]
+    ps, frames, imgs, evs = [], [], [], []
+    host = []
+    for i, (nt, ny, nx, k_lo) in enumerate(specs):
+        f = gen_stack(100 + i, nt, ny, nx)
+        host.append(f)
+        ps.append(hh.Params(nx=nx, ny=ny, nt=nt, k_lo=k_lo, k_hi=nt - 1))
+        frames.append(to_dev(f))
+        imgs.append(torch.empty((ny, nx), dtype=torch.float32, device="cuda"))
+        evs.append(torch.empty(nt, dtype=torch.float64, device="cuda"))
+    ws = hh.alloc_workspace(hh.batch_workspace_bytes(ps))
+    hh.hh_pipeline_batch(ps, frames, imgs, ws, evals=evs)
+    for i, (nt, ny, nx, k_lo) in enumerate(specs):
+        say(f"batch stack {i}: {nt}x{ny}x{nx}")
+        M = to_np(imgs[i])
+        alone = _pipeline(hh, host[i], k_lo, nt - 1)[0]
+        assert np.array_equal(M, alone), f"stack {i} differs from its alone result"
+        r = oracle.pipeline_ref(host[i], LAM, Z, PITCH, k_lo, nt - 1)
+        assert rel(M, r["image"]) <= IMG_TOL
+        assert np.abs(to_np(evs[i]) - r["evals"]).max() <= 1e-6 * r["evals"][0]
+
+
+def test_pipeline_batch_repeated_launch(hh):
+    # a prepared batch relaunched gives bit-identical images
+    import torch
+    ps = [hh.Params(nx=64, ny=64, nt=32, k_lo=2, k_hi=31) for _ in range(3)]
+    frames = [to_dev(gen_stack(200 + i, 32, 64, 64)) for i in range(3)]
+    imgs = [torch.empty((64, 64), dtype=torch.float32, device="cuda") for _ in range(3)]
+    ws = hh.alloc_workspace(hh.batch_workspace_bytes(ps))
+    b = hh.Batch(ps, frames, imgs, ws)
+    b.run()
+    first = [to_np(x).copy() for x in imgs]
+    b.run()
+    for a, x in zip(first, imgs):
+        assert np.array_equal(a, to_np(x))
