@@ -44,6 +44,7 @@ def algorithmic_bytes(kernel: str, launches_per_step: int) -> float:
         "fresnel_rows": 10.0 * npf,
         "fresnel_cols": 16.0 * npf,
         "gram_partial": 8.0 * npf,
+        "gram_partial_lp": 8.0 * npf,
         "project_complement": 8.0 * npf + 4.0 * NY * NX,
         "project_direct": 8.0 * npf + 4.0 * NY * NX,
     }.get(kernel)
@@ -88,6 +89,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--batch", type=int, default=16,
                     help="stacks per step, processed by one hh_pipeline_batch call (1 = hh_pipeline)")
+    ap.add_argument("--precision", default="fp32",
+                    help="arithmetic of the covariance contraction: fp32, bf16, fp16, bf16x3, fp16x3, fp8e4m3")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -115,7 +118,10 @@ def main():
     print("bench: generating 4 synthetic 32x1024x1024 stacks", file=sys.stderr, flush=True)
     host = [gen_stack(s, NT, NY, NX) for s in range(4)]
     frames = [torch.from_numpy(f).to(dev) for f in host]
-    p = hh.Params(nx=NX, ny=NY, nt=NT, k_lo=K_LO, k_hi=K_HI)
+    if args.precision not in hh.PRECISIONS:
+        print(f"bench.py: unknown --precision {args.precision}; one of {sorted(hh.PRECISIONS)}", file=sys.stderr)
+        sys.exit(2)
+    p = hh.Params(nx=NX, ny=NY, nt=NT, k_lo=K_LO, k_hi=K_HI, precision=hh.PRECISIONS[args.precision])
     B = max(1, args.batch)
     ws1 = hh.alloc_workspace(hh.workspace_bytes(p), dev)
     img1 = torch.empty((NY, NX), dtype=torch.float32, device=dev)
@@ -204,11 +210,11 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": value / PAPER_INTERFEROGRAMS_PER_S,
-        "dtype": "f32",
+        "dtype": "f32" if args.precision == "fp32" else f"f32 ({args.precision} covariance operands)",
         "data": "synthetic",
         "config": {"workload": "one 32x1024x1024 uint16 stack per step (4 seeded stacks rotated), "
-                               "lambda 785 nm, pitch 20 um, z 0.3 m, PCs 2..31, FP32",
-                   "stacks_per_s": value / NT, "precision": "fp32", "jacobi_sweeps": sweeps,
+                               f"lambda 785 nm, pitch 20 um, z 0.3 m, PCs 2..31, {args.precision}",
+                   "stacks_per_s": value / NT, "precision": args.precision, "jacobi_sweeps": sweeps,
                    "stacks_per_step": B, "ms_per_stack": ms_per_step / B},
         "roofline": roofline,
         "stack_roofline": {"bytes_per_stack": STACK_BYTES,

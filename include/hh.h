@@ -53,14 +53,20 @@ enum {
   HH_E_NOT_CONVERGED = 5  /* reserved for host-side reporting of info < 0 */
 };
 
-/* Arithmetic of the covariance and projection contractions. */
+/* Arithmetic of the covariance contraction of step (b), Eq. (4).  In every form
+ * the stack is split per pixel as H = m 1^T + R (m the pixel's temporal mean)
+ * and the rank-one terms of C are carried in FP32/FP64; the forms differ in the
+ * operands of the R^H R contraction.  Every form reads the FP32 hologram, so
+ * HBM traffic is the same; the low-precision forms trade accuracy for MFMA and
+ * register work.  Forms other than HH_FP32 require nt <= 32 (else
+ * HH_E_UNSUPPORTED).  The projection of step (d) is FP32 in every form. */
 enum {
-  HH_FP32 = 0,      /* FP32 products, short FP32 partial sums, FP64 reduction */
-  HH_BF16 = 1,      /* BF16 operands on MFMA, FP32 accumulation */
-  HH_FP16 = 2,      /* FP16 operands (power-of-two stack scale) on MFMA */
-  HH_BF16X3 = 3,    /* hi/lo BF16 split, three MFMA products */
-  HH_FP16X3 = 4,    /* hi/lo FP16 split, three MFMA products */
-  HH_FP8E4M3 = 5    /* OCP e4m3 operands, per-frame power-of-two scales */
+  HH_FP32 = 0,      /* FP32 operands, FP32 sums of <= 512 products, FP64 reduction */
+  HH_BF16 = 1,      /* BF16 operands (round to nearest even) on MFMA, FP32 accumulation */
+  HH_FP16 = 2,      /* FP16 operands, one power-of-two scale per 256 pixels */
+  HH_BF16X3 = 3,    /* R = hi + lo in BF16, hi*hi + hi*lo + lo*hi on MFMA */
+  HH_FP16X3 = 4,    /* R = hi + lo in FP16 (scaled as HH_FP16), three MFMA products */
+  HH_FP8E4M3 = 5    /* OCP e4m3 operands, power-of-two scale per frame and 256 pixels */
 };
 
 /* How the image of Eq. (7) is evaluated (same result up to rounding). */
@@ -80,7 +86,7 @@ typedef struct {
   int32_t k_lo, k_hi;   /* kept components of I_f (Eq. (6)), 0-based, inclusive,
                            counted in DESCENDING eigenvalue order: 0 <= k_lo <= k_hi < nt.
                            The paper's 1-based ascending n1..n2 maps to nt-n2..nt-n1. */
-  int32_t precision;    /* HH_FP32 ... (contractions of steps (b) and (d)) */
+  int32_t precision;    /* HH_FP32 ... (covariance contraction of step (b)) */
   int32_t proj_mode;    /* HH_PROJ_AUTO / _DIRECT / _COMPLEMENT */
   int32_t reserved;     /* must be 0 */
 } hh_params;
@@ -185,6 +191,54 @@ size_t hh_batch_workspace_bytes(const hh_params *p, int32_t n);
  */
 hh_status hh_pipeline_batch(const hh_params *p, int32_t n, const hh_stack *stacks, void *workspace,
                             size_t ws_bytes, void *stream);
+
+/* One hologram stack of hh_analyze_batch: its input, its image and optional eigen-outputs. */
+typedef struct {
+  const float *holo;      /* complex64 interleaved [nt][ny][nx] input (Fresnel holograms, step (a)),
+                             16-byte aligned */
+  float *image;           /* float32 [ny][nx] output */
+  double *evals;          /* float64 [nt] output, or NULL */
+  double *evecs;          /* complex128 [nt][nt] output, or NULL */
+  int32_t *info;          /* int32 [1] output (Jacobi sweeps, -1 = not converged), or NULL */
+} hh_window;
+
+/* Bytes of workspace hh_analyze_batch needs for the n stacks described by p[0..n-1]
+   (0 if any p[i] is invalid or n < 1). */
+size_t hh_analyze_batch_workspace_bytes(const hh_params *p, int32_t n);
+
+/*
+ * Steps (b)-(e) (Eqs. (4)-(7)) on n hologram stacks the caller already holds in
+ * device memory, e.g. windows of a ring of Fresnel holograms that a stream of
+ * frames fills with hh_fresnel, so that frames shared by overlapping windows are
+ * transformed once.  Every stack's covariance, then one launch for all n
+ * eigenproblems, then every stack's projection and image; each result is what
+ * hh_covariance + hh_eigh + hh_project_render give for that stack alone.
+ * Uses nx, ny, nt, k_lo, k_hi, precision, proj_mode of each p[i] (the optics are
+ * not read).  The holograms are only read.
+ *   p, wins   : host arrays of n entries (read during the call only).
+ *   workspace : at least hh_analyze_batch_workspace_bytes(p, n) bytes, 256-byte aligned.
+ * 1 <= n <= 4096.  Errors as hh_pipeline_batch.
+ */
+hh_status hh_analyze_batch(const hh_params *p, int32_t n, const hh_window *wins, void *workspace,
+                           size_t ws_bytes, void *stream);
+
+/*
+ * The work of one hh_pipeline_batch call, captured once as a HIP graph and
+ * replayed with one launch (steps (a)-(e) on n uneven stacks; no allocation or
+ * host work per replay).  The pointers in p/stacks/workspace are baked into the
+ * graph: every replay reads the CURRENT contents of the same frame buffers and
+ * rewrites the same outputs, so a caller refills the frames between replays.
+ * The buffers must outlive the graph; replays on one workspace must not overlap.
+ * hh_graph_create validates exactly as hh_pipeline_batch does, enqueues nothing
+ * on any caller stream, and sets *out (NULL on error).
+ */
+typedef struct hh_graph hh_graph;
+hh_status hh_graph_create(const hh_params *p, int32_t n, const hh_stack *stacks, void *workspace,
+                          size_t ws_bytes, hh_graph **out);
+/* One replay on `stream`; returns without synchronising. */
+hh_status hh_graph_launch(hh_graph *g, void *stream);
+/* Frees the graph (NULL is ignored).  Not while a replay may still run. */
+void hh_graph_destroy(hh_graph *g);
 
 /*
  * Fourier demodulation, Eqs. (8)-(9) (the paper's comparison method):

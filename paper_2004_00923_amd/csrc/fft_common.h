@@ -101,9 +101,11 @@ __host__ __device__ constexpr int fft_npasses(int N, int E) {
 // LDS slot of logical element e: one pad slot per 32 elements spreads the banks.
 __host__ __device__ constexpr int fft_pad(int e) { return e + (e >> 5); }
 
-template <int N>
+__host__ __device__ constexpr int fft_e(int N, int EP) { return N < EP ? N : EP; }
+
+template <int N, int EP = 16>
 struct FftCfg {
-  static constexpr int E = N < 16 ? N : 16;
+  static constexpr int E = N < EP ? N : EP;
   static constexpr int T = N / E;
   static constexpr int P = fft_npasses(N, E);
   static constexpr int LDSN = fft_pad(N - 1) + 1;  // LDS slots per transform
@@ -113,12 +115,12 @@ struct FftCfg {
 // sequence entering pass P; on return v[i] = X[t + T*i] (natural order).
 // slot(e) maps a logical element of this transform to its LDS slot; every
 // thread of the workgroup must call this (it contains barriers).
-template <int N, int P, class Slot>
-__device__ __forceinline__ void fft_passes(float2 (&v)[FftCfg<N>::E], int t, const float2 *__restrict__ tw,
+template <int N, int EP, int P, class Slot>
+__device__ __forceinline__ void fft_passes(float2 (&v)[fft_e(N, EP)], int t, const float2 *__restrict__ tw,
                                            float2 *lds, Slot slot) {
-  constexpr int E = FftCfg<N>::E, T = FftCfg<N>::T;
+  constexpr int E = FftCfg<N, EP>::E, T = FftCfg<N, EP>::T;
   constexpr int R = fft_radix(N, E, P), NS = fft_ns(N, E, P), B = E / R;
-  constexpr bool last = (P == FftCfg<N>::P - 1);
+  constexpr bool last = (P == FftCfg<N, EP>::P - 1);
 #pragma unroll
   for (int b = 0; b < B; ++b) {
     const int j = t + T * b;
@@ -144,8 +146,8 @@ __device__ __forceinline__ void fft_passes(float2 (&v)[FftCfg<N>::E], int t, con
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < E; ++i) v[i] = lds[slot(t + T * i)];
-    if constexpr (P + 1 < FftCfg<N>::P - 1) __syncthreads();  // reads done before the next pass writes
-    fft_passes<N, P + 1>(v, t, tw, lds, slot);
+    if constexpr (P + 1 < FftCfg<N, EP>::P - 1) __syncthreads();  // reads done before the next pass writes
+    fft_passes<N, EP, P + 1>(v, t, tw, lds, slot);
   }
 }
 

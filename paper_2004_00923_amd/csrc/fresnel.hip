@@ -64,9 +64,9 @@ __global__ __launch_bounds__(ROWS *FftCfg<N>::T) void fresnel_rows(
   }
   if constexpr (FftCfg<N>::P > 1) {
     __shared__ float2 lds[ROWS * FftCfg<N>::LDSN];
-    fft_passes<N, 0>(v, t, tw, lds + r * FftCfg<N>::LDSN, RowSlot{});
+    fft_passes<N, 16, 0>(v, t, tw, lds + r * FftCfg<N>::LDSN, RowSlot{});
   } else {
-    fft_passes<N, 0>(v, t, tw, (float2 *)nullptr, RowSlot{});
+    fft_passes<N, 16, 0>(v, t, tw, (float2 *)nullptr, RowSlot{});
   }
   if (live) {
 #pragma unroll
@@ -89,9 +89,9 @@ __global__ __launch_bounds__(W *FftCfg<N>::T) void fresnel_cols(float2 *__restri
   for (int i = 0; i < E; ++i) v[i] = live ? base[(size_t)(t + T * i) * nx] : make_float2(0.f, 0.f);
   if constexpr (FftCfg<N>::P > 1) {
     __shared__ float2 lds[W * FftCfg<N>::LDSN];
-    fft_passes<N, 0>(v, t, tw, lds, ColSlot<W>{c});
+    fft_passes<N, 16, 0>(v, t, tw, lds, ColSlot<W>{c});
   } else {
-    fft_passes<N, 0>(v, t, tw, (float2 *)nullptr, ColSlot<W>{c});
+    fft_passes<N, 16, 0>(v, t, tw, (float2 *)nullptr, ColSlot<W>{c});
   }
   if (live) {
 #pragma unroll

@@ -297,6 +297,263 @@ __global__ __launch_bounds__(256) void gram_partial64(const float2 *__restrict__
   }
 }
 
+
+// ---------------------------------------------------------------------------
+// Low-precision forms of the R^H R contraction (n_t <= 32).  R = H - m is formed
+// in FP32 exactly as above (the rank-one terms stay FP32/FP64), then rounded to
+// the operand format, and R^H R runs on v_mfma_f32_16x16x32_{bf16,f16} or
+// v_mfma_f32_16x16x32_fp8_fp8 with FP32 accumulation.  SPLIT keeps r = hi + lo
+// and sums hi*hi' + hi*lo' + lo*hi' (the lo*lo' term is dropped).  FP16 uses a
+// power-of-two scale per wave and FP8 (OCP e4m3, max 448) one per wave and
+// frame, both chosen from a first pass over the wave's pixels so that the
+// largest |Re|, |Im| fits; the scales are undone exactly when the partial sums
+// are converted to FP64.
+// Lane (f, kq) holds frames f and 16 + f of 8 pixels per 32-pixel step: element e
+// is pixel 8 (e / 2) + 2 kq + (e % 2), so each 16-byte load instruction covers 64
+// contiguous bytes of 16 frames.
+enum { kLpBF16 = 0, kLpFP16 = 1, kLpFP8 = 2 };
+
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+typedef _Float16 v8h __attribute__((ext_vector_type(8)));
+
+__device__ __forceinline__ unsigned short bf16_bits(float x) {  // round to nearest even
+  unsigned u = __float_as_uint(x);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (unsigned short)(u >> 16);
+}
+__device__ __forceinline__ float bf16_val(unsigned short b) { return __uint_as_float((unsigned)b << 16); }
+
+template <int FMT>
+struct LpOp;
+template <>
+struct LpOp<kLpBF16> {
+  typedef v8bf vec;
+  union U {
+    vec v;
+    unsigned short s[8];
+  };
+  __device__ static float put(U &u, int e, float x) {
+    const unsigned short b = bf16_bits(x);
+    u.s[e] = b;
+    return bf16_val(b);
+  }
+  __device__ static v4f mma(const vec &a, const vec &b, v4f c) { return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0); }
+};
+template <>
+struct LpOp<kLpFP16> {
+  typedef v8h vec;
+  union U {
+    vec v;
+    _Float16 s[8];
+  };
+  __device__ static float put(U &u, int e, float x) {
+    const _Float16 h = (_Float16)x;
+    u.s[e] = h;
+    return (float)h;
+  }
+  __device__ static v4f mma(const vec &a, const vec &b, v4f c) { return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0); }
+};
+template <>
+struct LpOp<kLpFP8> {
+  typedef long vec;
+  union U {
+    long v;
+    unsigned char s[8];
+  };
+  // OCP e4m3 round-to-nearest-even of a value already scaled into [-448, 448]
+  __device__ static float put(U &u, int e, float x) {
+    const int pk = __builtin_amdgcn_cvt_pk_fp8_f32(x, 0.0f, 0, false);
+    u.s[e] = (unsigned char)(pk & 0xFF);
+    return __builtin_amdgcn_cvt_f32_fp8(pk, 0);
+  }
+  __device__ static v4f mma(const vec &a, const vec &b, v4f c) { return __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(a, b, c, 0, 0, 0); }
+};
+
+__device__ __forceinline__ float max16(float v) {
+  v = fmaxf(v, dpp<0xB1>(v));
+  v = fmaxf(v, dpp<0x4E>(v));
+  v = fmaxf(v, dpp<0x141>(v));
+  v = fmaxf(v, dpp<0x140>(v));
+  return v;
+}
+// max over the four 16-lane rows (lanes f, f+16, f+32, f+48)
+__device__ __forceinline__ float max_rows(float v) {
+  v = fmaxf(v, __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(v), 0x401F)));  // xor 16
+  v = fmaxf(v, __shfl_xor(v, 32));
+  return v;
+}
+// power of two s with max * s <= lim (1 for max == 0)
+__device__ __forceinline__ float pow2_scale(float mx, float lim) {
+  if (!(mx > 0.f)) return 1.f;
+  int e;
+  frexpf(lim / mx, &e);  // lim/mx = f * 2^e, f in [0.5, 1)
+  return ldexpf(1.f, e - 1);
+}
+
+template <int FMT, bool SPLIT>
+__global__ __launch_bounds__(256) void gram_partial_lp(const float2 *__restrict__ H, int nt, long long npix,
+                                                       double *__restrict__ partial) {
+  constexpr int D = 32;
+  typedef LpOp<FMT> Op;
+  typedef typename Op::U U;
+  __shared__ double red[2 * D * D];
+  __shared__ double2 ared[4][4][D];
+  __shared__ double mmred[4][4];
+  __shared__ float fscale[4][D];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int f = lane & 15, kq = lane >> 4;
+  const float inv_nt = 1.0f / (float)nt;
+  const long long p0 = ((long long)blockIdx.x * 4 + wave) * kGramPxPerWave;
+  const bool v0 = f < nt, v1 = (16 + f) < nt;
+  const float4 *s0p = reinterpret_cast<const float4 *>(H + (long long)(v0 ? f : 0) * npix + p0) + kq;
+  const float4 *s1p = reinterpret_cast<const float4 *>(H + (long long)(v1 ? 16 + f : 0) * npix + p0) + kq;
+
+  auto load_step = [&](int j, float2 (&x0)[8], float2 (&x1)[8]) {
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+      const bool in = p0 + 32 * j + 8 * g + 2 * kq < npix;
+      const float4 a = (v0 && in) ? s0p[16 * j + 4 * g] : make_float4(0.f, 0.f, 0.f, 0.f);
+      const float4 b = (v1 && in) ? s1p[16 * j + 4 * g] : make_float4(0.f, 0.f, 0.f, 0.f);
+      x0[2 * g] = make_float2(a.x, a.y);
+      x0[2 * g + 1] = make_float2(a.z, a.w);
+      x1[2 * g] = make_float2(b.x, b.y);
+      x1[2 * g + 1] = make_float2(b.z, b.w);
+    }
+  };
+  constexpr int STEPS = kGramPxPerWave / 32;
+
+  // pass A (FP16, FP8): largest |Re|, |Im| of R, per wave or per wave and frame
+  float sc0 = 1.f, sc1 = 1.f;
+  if constexpr (FMT != kLpBF16) {
+    float m0 = 0.f, m1 = 0.f;
+    for (int j = 0; j < STEPS; ++j) {
+      float2 x0[8], x1[8];
+      load_step(j, x0, x1);
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const float mr = sum16(x0[e].x + x1[e].x) * inv_nt, mi = sum16(x0[e].y + x1[e].y) * inv_nt;
+        if (v0) m0 = fmaxf(m0, fmaxf(fabsf(x0[e].x - mr), fabsf(x0[e].y - mi)));
+        if (v1) m1 = fmaxf(m1, fmaxf(fabsf(x1[e].x - mr), fabsf(x1[e].y - mi)));
+      }
+    }
+    m0 = max_rows(m0);
+    m1 = max_rows(m1);
+    if constexpr (FMT == kLpFP16) {
+      const float mw = max16(fmaxf(m0, m1));  // whole wave
+      sc0 = sc1 = pow2_scale(mw, 16384.f);     // headroom for the hi/lo residual and partial sums
+    } else {
+      sc0 = pow2_scale(m0, 448.f);
+      sc1 = pow2_scale(m1, 448.f);
+    }
+  }
+  if (kq == 0) {
+    fscale[wave][f] = sc0;
+    fscale[wave][16 + f] = sc1;
+  }
+
+  v4f S00 = {0.f, 0.f, 0.f, 0.f}, S01 = S00, S11 = S00, Q00 = S00, Q01 = S00, Q10 = S00, Q11 = S00;
+  double2 a0 = make_double2(0.0, 0.0), a1 = a0;
+  double mm = 0.0;
+  for (int j = 0; j < STEPS; ++j) {
+    float2 x0[8], x1[8];
+    load_step(j, x0, x1);
+    U r0h, i0h, r1h, i1h, r0l, i0l, r1l, i1l;
+    float a0r = 0.f, a0i = 0.f, a1r = 0.f, a1i = 0.f, mmf = 0.f;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const float mr = sum16(x0[e].x + x1[e].x) * inv_nt, mi = sum16(x0[e].y + x1[e].y) * inv_nt;
+      mmf += mr * mr + mi * mi;
+      float2 q0 = x0[e], q1 = x1[e];
+      if (v0) {
+        q0.x -= mr;
+        q0.y -= mi;
+      }
+      if (v1) {
+        q1.x -= mr;
+        q1.y -= mi;
+      }
+      a0r += mr * q0.x + mi * q0.y;
+      a0i += mr * q0.y - mi * q0.x;
+      a1r += mr * q1.x + mi * q1.y;
+      a1i += mr * q1.y - mi * q1.x;
+      const float hr0 = Op::put(r0h, e, q0.x * sc0), hi0 = Op::put(i0h, e, q0.y * sc0);
+      const float hr1 = Op::put(r1h, e, q1.x * sc1), hi1 = Op::put(i1h, e, q1.y * sc1);
+      if constexpr (SPLIT) {
+        Op::put(r0l, e, q0.x * sc0 - hr0);
+        Op::put(i0l, e, q0.y * sc0 - hi0);
+        Op::put(r1l, e, q1.x * sc1 - hr1);
+        Op::put(i1l, e, q1.y * sc1 - hi1);
+      }
+    }
+    a0.x += a0r;
+    a0.y += a0i;
+    a1.x += a1r;
+    a1.y += a1i;
+    mm += mmf;
+    auto prod = [&](const U &xh, const U &xl, const U &yh, const U &yl, v4f acc) {
+      acc = Op::mma(xh.v, yh.v, acc);
+      if constexpr (SPLIT) {
+        acc = Op::mma(xh.v, yl.v, acc);
+        acc = Op::mma(xl.v, yh.v, acc);
+      }
+      return acc;
+    };
+    S00 = prod(r0h, r0l, r0h, r0l, S00);
+    S00 = prod(i0h, i0l, i0h, i0l, S00);
+    Q00 = prod(r0h, r0l, i0h, i0l, Q00);
+    S01 = prod(r0h, r0l, r1h, r1l, S01);
+    S01 = prod(i0h, i0l, i1h, i1l, S01);
+    S11 = prod(r1h, r1l, r1h, r1l, S11);
+    S11 = prod(i1h, i1l, i1h, i1l, S11);
+    Q01 = prod(r0h, r0l, i1h, i1l, Q01);
+    Q10 = prod(r1h, r1l, i0h, i0l, Q10);
+    Q11 = prod(r1h, r1l, i1h, i1l, Q11);
+  }
+
+  for (int i = tid; i < 2 * D * D; i += 256) red[i] = 0.0;
+  ared[wave][kq][f] = a0;
+  ared[wave][kq][16 + f] = a1;
+  if (f == 0) mmred[wave][kq] = mm;
+  __syncthreads();
+  for (int w = 0; w < 4; ++w) {
+    if (wave == w) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = 4 * kq + r, jj = f;  // 16x16 accumulator layout
+        auto un = [&](int a, int b) { return 1.0 / ((double)fscale[w][a] * (double)fscale[w][b]); };
+        red[i * D + jj] += (double)S00[r] * un(i, jj);
+        red[D * D + i * D + jj] += (double)Q00[r] * un(i, jj);
+        red[i * D + 16 + jj] += (double)S01[r] * un(i, 16 + jj);
+        red[(16 + i) * D + 16 + jj] += (double)S11[r] * un(16 + i, 16 + jj);
+        red[D * D + i * D + 16 + jj] += (double)Q01[r] * un(i, 16 + jj);
+        red[D * D + (16 + i) * D + jj] += (double)Q10[r] * un(16 + i, jj);
+        red[D * D + (16 + i) * D + 16 + jj] += (double)Q11[r] * un(16 + i, 16 + jj);
+      }
+    }
+    __syncthreads();
+  }
+  double *out = partial + (size_t)blockIdx.x * partial_len(D);
+  for (int i = tid; i < 2 * D * D; i += 256) out[i] = red[i];
+  if (tid < D) {
+    double ar = 0.0, ai = 0.0;
+    for (int w = 0; w < 4; ++w)
+      for (int q = 0; q < 4; ++q) {
+        ar += ared[w][q][tid].x;
+        ai += ared[w][q][tid].y;
+      }
+    out[2 * D * D + tid] = ar;
+    out[2 * D * D + D + tid] = ai;
+  }
+  if (tid == 0) {
+    double t = 0.0;
+    for (int w = 0; w < 4; ++w)
+      for (int q = 0; q < 4; ++q) t += mmred[w][q];
+    out[2 * D * D + 2 * D] = t;
+    out[2 * D * D + 2 * D + 1] = 0.0;
+  }
+}
+
 // out[g2][l] = sum over g in segment g2 of in[g][l], segments in increasing g.
 __global__ __launch_bounds__(256) void gram_reduce(const double *__restrict__ in, int G, int L, int G2,
                                                    double *__restrict__ out) {
@@ -350,8 +607,18 @@ GramLayout gram_layout(int nt, long long npix) {
 }
 
 hipError_t launch_gram(const GramLayout &L, const float2 *holo, int nt, long long npix, double *partial,
-                       double *partial2, double *cov, hipStream_t s) {
-  {
+                       double *partial2, double *cov, hipStream_t s, int precision) {
+  if (precision != HH_FP32 && nt <= 32) {
+    ProfScope ps("gram_partial_lp", s);
+    const dim3 g(L.groups), b(256);
+    switch (precision) {
+      case HH_BF16: hipLaunchKernelGGL((gram_partial_lp<kLpBF16, false>), g, b, 0, s, holo, nt, npix, partial); break;
+      case HH_BF16X3: hipLaunchKernelGGL((gram_partial_lp<kLpBF16, true>), g, b, 0, s, holo, nt, npix, partial); break;
+      case HH_FP16: hipLaunchKernelGGL((gram_partial_lp<kLpFP16, false>), g, b, 0, s, holo, nt, npix, partial); break;
+      case HH_FP16X3: hipLaunchKernelGGL((gram_partial_lp<kLpFP16, true>), g, b, 0, s, holo, nt, npix, partial); break;
+      default: hipLaunchKernelGGL((gram_partial_lp<kLpFP8, false>), g, b, 0, s, holo, nt, npix, partial); break;
+    }
+  } else {
     ProfScope ps("gram_partial", s);
     if (nt <= 16)
       hipLaunchKernelGGL(gram_partial16<false>, dim3(L.groups), dim3(256), 0, s, holo, nt, npix, partial);

@@ -7,6 +7,7 @@
 #include <cstring>
 #include <map>
 #include <mutex>
+#include <new>
 #include <string>
 #include <tuple>
 #include <vector>
@@ -67,6 +68,8 @@ hipEvent_t prof_event() {
 ProfScope::ProfScope(const char *n, hipStream_t s) : name(n), stream(s) {
   std::lock_guard<std::mutex> g(g_prof_mu);
   if (!g_prof_on) return;
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return;  // not in graphs
   hipEvent_t e = prof_event();
   if (e && hipEventRecord(e, s) == hipSuccess) ev0 = e;
 }
@@ -210,7 +213,8 @@ hh_status check_select(const hh_params *p) {
 
 hh_status check_precision(const hh_params *p) {
   if (p->precision < HH_FP32 || p->precision > HH_FP8E4M3) return fail(HH_E_INVALID, "precision=%d unknown", p->precision);
-  if (p->precision != HH_FP32) return fail(HH_E_UNSUPPORTED, "precision form %d not built", p->precision);
+  if (p->precision != HH_FP32 && p->nt > 32)
+    return fail(HH_E_UNSUPPORTED, "precision form %d is built for nt <= 32 (nt=%d)", p->precision, p->nt);
   return HH_OK;
 }
 
@@ -221,12 +225,14 @@ struct PipeLayout {
   size_t holo = 0, part = 0, part2 = 0, cov = 0, evals = 0, evecs = 0, info = 0, total = 0;
 };
 
-PipeLayout pipe_layout(const hh_params *p) {
+// with_holo = false: the layout of steps (b)-(e) on a hologram stack the caller holds
+PipeLayout pipe_layout(const hh_params *p, bool with_holo = true) {
   PipeLayout L;
   const long long npix = (long long)p->nx * p->ny;
   L.g = gram_layout(p->nt, npix);
   size_t o = 0;
-  L.holo = o; o = align_up(o + (size_t)p->nt * npix * sizeof(float2));
+  L.holo = o;
+  if (with_holo) o = align_up(o + (size_t)p->nt * npix * sizeof(float2));
   L.part = o; o = align_up(o + L.g.partial_bytes);
   L.part2 = o; o = align_up(o + L.g.partial2_bytes);
   L.cov = o; o = align_up(o + (size_t)p->nt * p->nt * 2 * sizeof(double));
@@ -235,6 +241,84 @@ PipeLayout pipe_layout(const hh_params *p) {
   L.info = o; o = align_up(o + sizeof(int));
   L.total = o;
   return L;
+}
+
+constexpr int kMaxBatch = 4096;
+
+// One stack of a batch: either frames (steps (a)-(e)) or a hologram stack (steps (b)-(e)).
+struct BatchItem {
+  const uint16_t *frames;
+  const float2 *holo;
+  float *image;
+  double *evals, *evecs;
+  int32_t *info;
+};
+
+size_t batch_ws_bytes(const hh_params *p, int32_t n, bool with_holo) {
+  if (!p || n < 1 || n > kMaxBatch) return 0;
+  size_t total = 0;
+  for (int i = 0; i < n; ++i) {
+    if (check_stack(p + i) || check_select(p + i) || (with_holo && check_optics(p + i))) return 0;
+    total += align_up(pipe_layout(p + i, with_holo).total);
+  }
+  return total;
+}
+
+// Validates every item, then enqueues: per stack the Fresnel transform (frames
+// given) and the covariance; one launch for all eigenproblems; per stack the
+// projection and image.
+hh_status run_batch(const hh_params *p, int n, const BatchItem *it, void *workspace, size_t ws_bytes, hipStream_t s,
+                    const char *who) {
+  const bool with_holo = it[0].frames != nullptr;
+  size_t need = 0;
+  for (int i = 0; i < n; ++i) {
+    hh_status st;
+    if ((with_holo && (st = check_optics(p + i))) || (st = check_stack(p + i)) || (st = check_select(p + i)) ||
+        (st = check_precision(p + i))) {
+      const std::string msg = g_err;
+      return fail(st, "stack %d: %s", i, msg.c_str());
+    }
+    if (!it[i].image) return fail(HH_E_INVALID, "stack %d: image must be non-NULL", i);
+    if (!aligned(it[i].image, 8) || (it[i].evals && !aligned(it[i].evals, 8)) ||
+        (it[i].evecs && !aligned(it[i].evecs, 16)) || (it[i].info && !aligned(it[i].info, 4)))
+      return fail(HH_E_INVALID, "stack %d: arrays misaligned", i);
+    need += align_up(pipe_layout(p + i, with_holo).total);
+  }
+  if (!workspace || ws_bytes < need || !aligned(workspace, 256))
+    return fail(HH_E_WORKSPACE, "%s workspace: need %zu bytes (256-byte aligned), got %zu", who, need, ws_bytes);
+  std::vector<const Plan *> plans(n, nullptr);
+  if (with_holo)
+    for (int i = 0; i < n; ++i)
+      if (!(plans[i] = get_plan(p[i]))) return HH_E_DEVICE;
+  std::vector<EighProblem> probs(n);
+  std::vector<const float2 *> H(n);
+  char *ws = static_cast<char *>(workspace);
+  hipError_t e = hipSuccess;
+  for (int i = 0; i < n && e == hipSuccess; ++i) {
+    const PipeLayout L = pipe_layout(p + i, with_holo);
+    const long long npix = (long long)p[i].nx * p[i].ny;
+    double *cov = reinterpret_cast<double *>(ws + L.cov);
+    if (with_holo) {
+      float2 *Hw = reinterpret_cast<float2 *>(ws + L.holo);
+      e = launch_fresnel(*plans[i], it[i].frames, p[i].nt, Hw, s);
+      H[i] = Hw;
+    } else {
+      H[i] = it[i].holo;
+    }
+    if (e == hipSuccess)
+      e = launch_gram(L.g, H[i], p[i].nt, npix, reinterpret_cast<double *>(ws + L.part),
+                      reinterpret_cast<double *>(ws + L.part2), cov, s, p[i].precision);
+    probs[i] = EighProblem{p[i].nt, cov, it[i].evals ? it[i].evals : reinterpret_cast<double *>(ws + L.evals),
+                           it[i].evecs ? it[i].evecs : reinterpret_cast<double *>(ws + L.evecs),
+                           it[i].info ? it[i].info : reinterpret_cast<int *>(ws + L.info)};
+    ws += align_up(L.total);
+  }
+  if (e == hipSuccess) e = launch_eigh_batch(probs.data(), n, 40, s);
+  for (int i = 0; i < n && e == hipSuccess; ++i)
+    e = launch_project(H[i], p[i].nt, (long long)p[i].nx * p[i].ny, probs[i].evecs, p[i].k_lo, p[i].k_hi,
+                       p[i].proj_mode, it[i].image, s);
+  if (e != hipSuccess) return device_fail(e, who);
+  return HH_OK;
 }
 
 size_t cov_ws_bytes(const hh_params *p) {
@@ -300,7 +384,8 @@ hh_status hh_covariance(const hh_params *p, const float *holo, double *cov, void
   const GramLayout g = gram_layout(p->nt, npix);
   char *ws = static_cast<char *>(workspace);
   hipError_t e = launch_gram(g, reinterpret_cast<const float2 *>(holo), p->nt, npix, reinterpret_cast<double *>(ws),
-                             reinterpret_cast<double *>(ws + align_up(g.partial_bytes)), cov, (hipStream_t)stream);
+                             reinterpret_cast<double *>(ws + align_up(g.partial_bytes)), cov, (hipStream_t)stream,
+                             p->precision);
   if (e != hipSuccess) return device_fail(e, "hh_covariance");
   return HH_OK;
 }
@@ -371,75 +456,116 @@ hh_status hh_pipeline(const hh_params *p, const uint16_t *frames, float *image, 
   hipError_t e = launch_fresnel(*pl, frames, p->nt, H, s);
   if (e == hipSuccess)
     e = launch_gram(L.g, H, p->nt, npix, reinterpret_cast<double *>(ws + L.part),
-                    reinterpret_cast<double *>(ws + L.part2), cov, s);
+                    reinterpret_cast<double *>(ws + L.part2), cov, s, p->precision);
   if (e == hipSuccess) e = launch_eigh(p->nt, cov, ev, V, inf, 40, s);
   if (e == hipSuccess) e = launch_project(H, p->nt, npix, V, p->k_lo, p->k_hi, p->proj_mode, image, s);
   if (e != hipSuccess) return device_fail(e, "hh_pipeline");
   return HH_OK;
 }
 
-size_t hh_batch_workspace_bytes(const hh_params *p, int32_t n) {
-  if (!p || n < 1 || n > 4096) return 0;
-  size_t total = 0;
-  for (int i = 0; i < n; ++i) {
-    if (check_optics(p + i) || check_stack(p + i) || check_select(p + i)) return 0;
-    total += align_up(pipe_layout(p + i).total);
-  }
-  return total;
-}
+size_t hh_batch_workspace_bytes(const hh_params *p, int32_t n) { return batch_ws_bytes(p, n, true); }
+
+size_t hh_analyze_batch_workspace_bytes(const hh_params *p, int32_t n) { return batch_ws_bytes(p, n, false); }
 
 hh_status hh_pipeline_batch(const hh_params *p, int32_t n, const hh_stack *stacks, void *workspace,
                             size_t ws_bytes, void *stream) {
   if (!p || !stacks) return fail(HH_E_INVALID, "params and stacks must be non-NULL");
-  if (n < 1 || n > 4096) return fail(HH_E_INVALID, "batch size n=%d must be in [1, 4096]", n);
-  size_t need = 0;
+  if (n < 1 || n > kMaxBatch) return fail(HH_E_INVALID, "batch size n=%d must be in [1, %d]", n, kMaxBatch);
+  std::vector<BatchItem> items(n);
   for (int i = 0; i < n; ++i) {
+    if (!stacks[i].frames) return fail(HH_E_INVALID, "stack %d: frames must be non-NULL", i);
+    if (!aligned(stacks[i].frames, 2)) return fail(HH_E_INVALID, "stack %d: frames misaligned", i);
+    items[i] = BatchItem{stacks[i].frames, nullptr, stacks[i].image, stacks[i].evals, stacks[i].evecs, stacks[i].info};
+  }
+  return run_batch(p, n, items.data(), workspace, ws_bytes, (hipStream_t)stream, "hh_pipeline_batch");
+}
+
+hh_status hh_analyze_batch(const hh_params *p, int32_t n, const hh_window *wins, void *workspace, size_t ws_bytes,
+                           void *stream) {
+  if (!p || !wins) return fail(HH_E_INVALID, "params and windows must be non-NULL");
+  if (n < 1 || n > kMaxBatch) return fail(HH_E_INVALID, "batch size n=%d must be in [1, %d]", n, kMaxBatch);
+  std::vector<BatchItem> items(n);
+  for (int i = 0; i < n; ++i) {
+    if (!wins[i].holo) return fail(HH_E_INVALID, "window %d: holo must be non-NULL", i);
+    if (!aligned(wins[i].holo, 16)) return fail(HH_E_INVALID, "window %d: holo must be 16-byte aligned", i);
+    items[i] = BatchItem{nullptr, reinterpret_cast<const float2 *>(wins[i].holo), wins[i].image, wins[i].evals,
+                         wins[i].evecs, wins[i].info};
+  }
+  return run_batch(p, n, items.data(), workspace, ws_bytes, (hipStream_t)stream, "hh_analyze_batch");
+}
+
+struct hh_graph {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  int n = 0;
+};
+
+hh_status hh_graph_create(const hh_params *p, int32_t n, const hh_stack *stacks, void *workspace, size_t ws_bytes,
+                          hh_graph **out) {
+  if (!out) return fail(HH_E_INVALID, "out must be non-NULL");
+  *out = nullptr;
+  if (!p || !stacks) return fail(HH_E_INVALID, "params and stacks must be non-NULL");
+  if (n < 1 || n > kMaxBatch) return fail(HH_E_INVALID, "batch size n=%d must be in [1, %d]", n, kMaxBatch);
+  std::vector<BatchItem> items(n);
+  for (int i = 0; i < n; ++i) {
+    if (!stacks[i].frames) return fail(HH_E_INVALID, "stack %d: frames must be non-NULL", i);
+    if (!aligned(stacks[i].frames, 2)) return fail(HH_E_INVALID, "stack %d: frames misaligned", i);
+    items[i] = BatchItem{stacks[i].frames, nullptr, stacks[i].image, stacks[i].evals, stacks[i].evecs, stacks[i].info};
     hh_status st;
-    if ((st = check_optics(p + i)) || (st = check_stack(p + i)) || (st = check_select(p + i)) ||
-        (st = check_precision(p + i))) {
+    if ((st = check_optics(p + i)) || (st = check_shape(p + i))) {
       const std::string msg = g_err;
       return fail(st, "stack %d: %s", i, msg.c_str());
     }
-    const hh_stack &sk = stacks[i];
-    if (!sk.frames || !sk.image) return fail(HH_E_INVALID, "stack %d: frames and image must be non-NULL", i);
-    if (!aligned(sk.frames, 2) || !aligned(sk.image, 8) || (sk.evals && !aligned(sk.evals, 8)) ||
-        (sk.evecs && !aligned(sk.evecs, 16)) || (sk.info && !aligned(sk.info, 4)))
-      return fail(HH_E_INVALID, "stack %d: arrays misaligned", i);
-    need += align_up(pipe_layout(p + i).total);
+    if (!get_plan(p[i])) return HH_E_DEVICE;  // tables allocated here, outside the capture
   }
-  if (!workspace || ws_bytes < need || !aligned(workspace, 256))
-    return fail(HH_E_WORKSPACE, "batch workspace: need %zu bytes (256-byte aligned), got %zu", need, ws_bytes);
-  std::vector<const Plan *> plans(n);
-  for (int i = 0; i < n; ++i)
-    if (!(plans[i] = get_plan(p[i]))) return HH_E_DEVICE;
-  hipStream_t s = (hipStream_t)stream;
-  std::vector<EighProblem> probs(n);
-  std::vector<char *> base(n);
-  char *ws = static_cast<char *>(workspace);
-  hipError_t e = hipSuccess;
-  for (int i = 0; i < n && e == hipSuccess; ++i) {
-    const PipeLayout L = pipe_layout(p + i);
-    base[i] = ws;
-    const long long npix = (long long)p[i].nx * p[i].ny;
-    float2 *H = reinterpret_cast<float2 *>(ws + L.holo);
-    double *cov = reinterpret_cast<double *>(ws + L.cov);
-    e = launch_fresnel(*plans[i], stacks[i].frames, p[i].nt, H, s);
-    if (e == hipSuccess)
-      e = launch_gram(L.g, H, p[i].nt, npix, reinterpret_cast<double *>(ws + L.part),
-                      reinterpret_cast<double *>(ws + L.part2), cov, s);
-    probs[i] = EighProblem{p[i].nt, cov, stacks[i].evals ? stacks[i].evals : reinterpret_cast<double *>(ws + L.evals),
-                           stacks[i].evecs ? stacks[i].evecs : reinterpret_cast<double *>(ws + L.evecs),
-                           stacks[i].info ? stacks[i].info : reinterpret_cast<int *>(ws + L.info)};
-    ws += align_up(L.total);
+  hipStream_t cs = nullptr;
+  hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+  if (e != hipSuccess) return device_fail(e, "hh_graph_create (stream)");
+  e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) {
+    (void)hipStreamDestroy(cs);
+    return device_fail(e, "hh_graph_create (begin capture)");
   }
-  if (e == hipSuccess) e = launch_eigh_batch(probs.data(), n, 40, s);
-  for (int i = 0; i < n && e == hipSuccess; ++i) {
-    const PipeLayout L = pipe_layout(p + i);
-    e = launch_project(reinterpret_cast<const float2 *>(base[i] + L.holo), p[i].nt, (long long)p[i].nx * p[i].ny,
-                       probs[i].evecs, p[i].k_lo, p[i].k_hi, p[i].proj_mode, stacks[i].image, s);
+  const hh_status st = run_batch(p, n, items.data(), workspace, ws_bytes, cs, "hh_graph_create");
+  hipGraph_t graph = nullptr;
+  const hipError_t e2 = hipStreamEndCapture(cs, &graph);
+  (void)hipStreamDestroy(cs);
+  if (st != HH_OK) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return st;
   }
-  if (e != hipSuccess) return device_fail(e, "hh_pipeline_batch");
+  if (e2 != hipSuccess) return device_fail(e2, "hh_graph_create (end capture)");
+  hipGraphExec_t exec = nullptr;
+  e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    (void)hipGraphDestroy(graph);
+    return device_fail(e, "hh_graph_create (instantiate)");
+  }
+  hh_graph *g = new (std::nothrow) hh_graph;
+  if (!g) {
+    (void)hipGraphExecDestroy(exec);
+    (void)hipGraphDestroy(graph);
+    return fail(HH_E_DEVICE, "hh_graph_create: out of host memory");
+  }
+  g->graph = graph;
+  g->exec = exec;
+  g->n = n;
+  *out = g;
   return HH_OK;
+}
+
+hh_status hh_graph_launch(hh_graph *g, void *stream) {
+  if (!g || !g->exec) return fail(HH_E_INVALID, "graph must be non-NULL");
+  const hipError_t e = hipGraphLaunch(g->exec, (hipStream_t)stream);
+  if (e != hipSuccess) return device_fail(e, "hh_graph_launch");
+  return HH_OK;
+}
+
+void hh_graph_destroy(hh_graph *g) {
+  if (!g) return;
+  if (g->exec) (void)hipGraphExecDestroy(g->exec);
+  if (g->graph) (void)hipGraphDestroy(g->graph);
+  delete g;
 }
 
 void hh_plan_cache_clear(void) {

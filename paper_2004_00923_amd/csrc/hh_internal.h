@@ -54,8 +54,10 @@ struct GramLayout {
 };
 constexpr int kGramPxPerWave = 256;  // pixels per wave (FP32 sums <= 256 px per accumulator)
 GramLayout gram_layout(int nt, long long npix);
+// precision: HH_FP32, or a low-precision form of the R^H R contraction (n_t <= 32;
+// larger stacks use the FP32 form).
 hipError_t launch_gram(const GramLayout &L, const float2 *holo, int nt, long long npix,
-                       double *partial, double *partial2, double *cov, hipStream_t s);
+                       double *partial, double *partial2, double *cov, hipStream_t s, int precision = HH_FP32);
 
 // Step (c): one workgroup per problem; problems are passed by value (kernel argument).
 struct EighProblem {

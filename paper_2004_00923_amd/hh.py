@@ -63,6 +63,11 @@ class hh_stack(ctypes.Structure):
                 ("evecs", ctypes.c_void_p), ("info", ctypes.c_void_p)]
 
 
+class hh_window(ctypes.Structure):
+    _fields_ = [("holo", ctypes.c_void_p), ("image", ctypes.c_void_p), ("evals", ctypes.c_void_p),
+                ("evecs", ctypes.c_void_p), ("info", ctypes.c_void_p)]
+
+
 class HHError(RuntimeError):
     def __init__(self, status: int, detail: str):
         super().__init__(f"hh status {status}: {detail}")
@@ -86,6 +91,13 @@ SIGNATURES = {
     "hh_batch_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(hh_params), ctypes.c_int32]),
     "hh_pipeline_batch": (ctypes.c_int32, [ctypes.POINTER(hh_params), ctypes.c_int32, ctypes.POINTER(hh_stack), _P,
                                            ctypes.c_size_t, _P]),
+    "hh_analyze_batch_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(hh_params), ctypes.c_int32]),
+    "hh_analyze_batch": (ctypes.c_int32, [ctypes.POINTER(hh_params), ctypes.c_int32, ctypes.POINTER(hh_window), _P,
+                                          ctypes.c_size_t, _P]),
+    "hh_graph_create": (ctypes.c_int32, [ctypes.POINTER(hh_params), ctypes.c_int32, ctypes.POINTER(hh_stack), _P,
+                                         ctypes.c_size_t, ctypes.POINTER(ctypes.c_void_p)]),
+    "hh_graph_launch": (ctypes.c_int32, [_P, _P]),
+    "hh_graph_destroy": (None, [_P]),
     "hh_status_string": (ctypes.c_char_p, [ctypes.c_int32]),
     "hh_last_error": (ctypes.c_char_p, []),
     "hh_plan_cache_clear": (None, []),
@@ -256,9 +268,68 @@ class Batch:
                                        self.ws.numel() * self.ws.element_size(), _stream(stream)))
 
 
+class Graph:
+    """hh_graph_create / hh_graph_launch / hh_graph_destroy: a batch captured once as
+    a HIP graph and replayed with one launch.  The tensors are kept alive with it."""
+
+    def __init__(self, ps, frames, images, workspace, evals=None, evecs=None, infos=None):
+        b = Batch(ps, frames, images, workspace, evals, evecs, infos)
+        self.keep = b
+        h = ctypes.c_void_p()
+        _check(lib().hh_graph_create(b.params, b.n, b.stacks, _ptr(workspace),
+                                     workspace.numel() * workspace.element_size(), ctypes.byref(h)))
+        self.h = h
+
+    def launch(self, stream=None):
+        _check(lib().hh_graph_launch(self.h, _stream(stream)))
+
+    def close(self):
+        if self.h:
+            import torch
+            torch.cuda.synchronize()
+            lib().hh_graph_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 def hh_pipeline_batch(ps, frames, images, workspace, evals=None, evecs=None, infos=None, stream=None):
     """Steps (a)-(e) on a batch of (possibly uneven) stacks; see include/hh.h."""
     Batch(ps, frames, images, workspace, evals, evecs, infos).run(stream)
+    return images
+
+
+def analyze_batch_workspace_bytes(ps) -> int:
+    return int(lib().hh_analyze_batch_workspace_bytes(_param_array(ps), len(ps)))
+
+
+def hh_analyze_batch(ps, holos, images, workspace, evals=None, evecs=None, infos=None, stream=None):
+    """Steps (b)-(e) on a batch of hologram stacks the caller holds (e.g. views of a
+    ring of holograms); see include/hh.h."""
+    import torch
+    n = len(ps)
+    if not (len(holos) == len(images) == n):
+        raise ValueError("one hologram stack and one image tensor per stack")
+    wins = (hh_window * n)()
+    for i, p in enumerate(ps):
+        _dev_tensor(holos[i], torch.complex64, (p.nt, p.ny, p.nx), f"holos[{i}]")
+        _dev_tensor(images[i], torch.float32, (p.ny, p.nx), f"images[{i}]")
+        if evals:
+            _dev_tensor(evals[i], torch.float64, (p.nt,), f"evals[{i}]")
+        if evecs:
+            _dev_tensor(evecs[i], torch.complex128, (p.nt, p.nt), f"evecs[{i}]")
+        if infos:
+            _dev_tensor(infos[i], torch.int32, (1,), f"infos[{i}]")
+        wins[i] = hh_window(holos[i].data_ptr(), images[i].data_ptr(),
+                            evals[i].data_ptr() if evals else None,
+                            evecs[i].data_ptr() if evecs else None,
+                            infos[i].data_ptr() if infos else None)
+    _check(lib().hh_analyze_batch(_param_array(ps), n, wins, _ptr(workspace),
+                                  workspace.numel() * workspace.element_size(), _stream(stream)))
     return images
 
 

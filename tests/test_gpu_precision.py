@@ -1,0 +1,102 @@
+"""GPU: the low-precision forms of the covariance contraction (step (b), Eq. (4))
+against the FP64 oracle.  Each form must stay within its own error bound on the
+image, the eigenvalues and C itself; the table printed here (run with -s) is the
+error table of the precision forms."""
+import numpy as np
+import pytest
+
+import oracle
+from gpu_util import LAM, PITCH, Z, rel, say, to_dev, to_np
+from paper_2004_00923_amd.synth import gen_stack
+
+pytestmark = pytest.mark.gpu
+
+# form name -> (enum attribute, bound on the normwise image error)
+FORMS = {
+    "fp32": ("HH_FP32", 1e-5),
+    "bf16x3": ("HH_BF16X3", 1e-4),
+    "fp16x3": ("HH_FP16X3", 1e-4),
+    "fp16": ("HH_FP16", 1e-2),
+    "bf16": ("HH_BF16", 5e-2),
+    "fp8e4m3": ("HH_FP8E4M3", 5e-1),
+}
+
+
+@pytest.fixture(scope="module")
+def hh():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    import paper_2004_00923_amd.hh as hh_mod
+    hh_mod.lib()
+    return hh_mod
+
+
+def _run(hh, frames, k_lo, k_hi, precision):
+    import torch
+    nt, ny, nx = frames.shape
+    p = hh.Params(nx=nx, ny=ny, nt=nt, k_lo=k_lo, k_hi=k_hi, precision=precision)
+    ws = hh.alloc_workspace(hh.workspace_bytes(p))
+    img = torch.empty((ny, nx), dtype=torch.float32, device="cuda")
+    ev = torch.empty(nt, dtype=torch.float64, device="cuda")
+    hh.hh_pipeline(p, to_dev(frames), img, ws, ev)
+    return to_np(img), to_np(ev)
+
+
+def _cov(hh, H32, precision):
+    import torch
+    nt, ny, nx = H32.shape
+    p = hh.Params(nx=nx, ny=ny, nt=nt, k_lo=0, k_hi=nt - 1, precision=precision)
+    ws = hh.alloc_workspace(hh.covariance_workspace_bytes(p))
+    C = torch.empty((nt, nt), dtype=torch.complex128, device="cuda")
+    hh.hh_covariance(p, to_dev(H32), C, ws)
+    return to_np(C)
+
+
+@pytest.mark.parametrize("ny,nx,seed", [(128, 128, 0), (1024, 1024, 0)])
+def test_precision_table(hh, ny, nx, seed):
+    f = gen_stack(seed, 32, ny, nx)
+    r = oracle.pipeline_ref(f, LAM, Z, PITCH, 2, 31)
+    H32 = oracle.fresnel_ref(f, LAM, Z, PITCH).astype(np.complex64)
+    C_ref = oracle.covariance_ref(H32.astype(np.complex128))
+    say(f"\nprecision forms, 32 x {ny} x {nx}, PCs 2..31 (normwise vs the FP64 oracle)")
+    say(f"{'form':>8} {'image':>10} {'lambda':>10} {'C':>10}")
+    bad = []
+    for name, (attr, bound) in FORMS.items():
+        prec = getattr(hh, attr)
+        M, w = _run(hh, f, 2, 31, prec)
+        e_img = rel(M, r["image"])
+        e_lam = float(np.abs(w - r["evals"]).max() / r["evals"][0])
+        e_c = rel(_cov(hh, H32, prec), C_ref)
+        say(f"{name:>8} {e_img:10.2e} {e_lam:10.2e} {e_c:10.2e}")
+        if not (np.isfinite(M).all() and e_img <= bound):
+            bad.append((name, e_img, bound))
+    assert not bad, f"forms over their image bound: {bad}"
+
+
+def test_precision_rejects_long_stacks(hh):
+    import torch
+    p = hh.Params(nx=16, ny=16, nt=33, k_lo=2, k_hi=32, precision=hh.HH_BF16)
+    ws = hh.alloc_workspace(1 << 20)
+    C = torch.empty((33, 33), dtype=torch.complex128, device="cuda")
+    H = torch.zeros((33, 16, 16), dtype=torch.complex64, device="cuda")
+    with pytest.raises(hh.HHError) as ei:
+        hh.hh_covariance(p, H, C, ws)
+    assert ei.value.status == hh.HH_E_UNSUPPORTED
+
+
+@pytest.mark.parametrize("attr", ["HH_BF16", "HH_FP16X3", "HH_FP8E4M3"])
+def test_precision_degenerate_inputs(hh, attr):
+    # a constant stack (R = 0: the per-pixel scales fall back to 1) and a stack
+    # with one bright frame (wide dynamic range) stay finite and close to the oracle
+    prec = getattr(hh, attr)
+    const = np.full((32, 64, 64), 1000, dtype=np.uint16)
+    M, w = _run(hh, const, 2, 31, prec)
+    r = oracle.pipeline_ref(const, LAM, Z, PITCH, 2, 31)
+    assert np.isfinite(M).all() and np.isfinite(w).all()
+    assert np.abs(w - r["evals"]).max() <= 1e-6 * r["evals"][0]
+    f = gen_stack(5, 32, 64, 64)
+    f[7] = np.minimum(f[7].astype(np.int64) * 2, 4095).astype(np.uint16)
+    M, w = _run(hh, f, 2, 31, prec)
+    r = oracle.pipeline_ref(f, LAM, Z, PITCH, 2, 31)
+    assert np.isfinite(M).all()
+    assert np.abs(w - r["evals"]).max() <= 5e-2 * r["evals"][0]
