@@ -53,20 +53,28 @@ enum {
   HH_E_NOT_CONVERGED = 5  /* reserved for host-side reporting of info < 0 */
 };
 
-/* Arithmetic of the covariance contraction of step (b), Eq. (4).  In every form
- * the stack is split per pixel as H = m 1^T + R (m the pixel's temporal mean)
- * and the rank-one terms of C are carried in FP32/FP64; the forms differ in the
- * operands of the R^H R contraction.  Every form reads the FP32 hologram, so
- * HBM traffic is the same; the low-precision forms trade accuracy for MFMA and
- * register work.  Forms other than HH_FP32 require nt <= 32 (else
- * HH_E_UNSUPPORTED).  The projection of step (d) is FP32 in every form. */
+/* Arithmetic of the covariance contraction of step (b), Eq. (4), and of the
+ * hologram storage.  In every form the stack is split per pixel as
+ * H = m 1^T + R (m a per-pixel reference, the temporal mean) and the rank-one
+ * terms of C are carried in FP32/FP64; the forms differ in the operands of the
+ * R^H R contraction.  Forms 1-5 read the FP32 hologram, so HBM traffic is that
+ * of HH_FP32; they trade accuracy for MFMA and register work.  HH_FP16_STORE
+ * changes what is stored: step (a) transforms the mean frame once (m, FP32) and
+ * each frame minus the mean (R, by linearity of Eq. (1)), and writes R as FP16
+ * scaled by s = 1 / (2 nx ny) (|R| <= nx ny 65535, so s R never overflows); the
+ * covariance runs on FP16 MFMA straight from R, and the projection of step (d)
+ * reads m + R / s.  It halves the hologram traffic and applies only to the
+ * entry points that start from frames (hh_pipeline, hh_pipeline_batch,
+ * hh_graph_create).  Forms other than HH_FP32 require nt <= 32 (else
+ * HH_E_UNSUPPORTED).  The projection is FP32/FP64 in every form. */
 enum {
   HH_FP32 = 0,      /* FP32 operands, FP32 sums of <= 512 products, FP64 reduction */
   HH_BF16 = 1,      /* BF16 operands (round to nearest even) on MFMA, FP32 accumulation */
   HH_FP16 = 2,      /* FP16 operands, one power-of-two scale per 256 pixels */
   HH_BF16X3 = 3,    /* R = hi + lo in BF16, hi*hi + hi*lo + lo*hi on MFMA */
   HH_FP16X3 = 4,    /* R = hi + lo in FP16 (scaled as HH_FP16), three MFMA products */
-  HH_FP8E4M3 = 5    /* OCP e4m3 operands, power-of-two scale per frame and 256 pixels */
+  HH_FP8E4M3 = 5,   /* OCP e4m3 operands, power-of-two scale per frame and 256 pixels */
+  HH_FP16_STORE = 6 /* hologram stored as FP32 mean + FP16 residual (see above) */
 };
 
 /* How the image of Eq. (7) is evaluated (same result up to rounding). */
@@ -86,7 +94,7 @@ typedef struct {
   int32_t k_lo, k_hi;   /* kept components of I_f (Eq. (6)), 0-based, inclusive,
                            counted in DESCENDING eigenvalue order: 0 <= k_lo <= k_hi < nt.
                            The paper's 1-based ascending n1..n2 maps to nt-n2..nt-n1. */
-  int32_t precision;    /* HH_FP32 ... (covariance contraction of step (b)) */
+  int32_t precision;    /* HH_FP32 ... HH_FP16_STORE (covariance contraction, hologram storage) */
   int32_t proj_mode;    /* HH_PROJ_AUTO / _DIRECT / _COMPLEMENT */
   int32_t reserved;     /* must be 0 */
 } hh_params;
@@ -152,6 +160,21 @@ hh_status hh_eigh_ex(int32_t nt, const double *cov, double *evals, double *evecs
  */
 hh_status hh_project_render(const hh_params *p, const float *holo, const double *evecs,
                             float *image, void *stream);
+
+/*
+ * The SVD-filtered stack, Eq. (3): Hf = H V I_f V^H with I_f the selector of
+ * components k_lo..k_hi (descending order), i.e. the stack with the dropped
+ * components removed, frame by frame, for temporal analysis downstream.  Its
+ * power sum_t |Hf[p][t]|^2 is the image of Eq. (7).
+ *   holo  : complex64 [nt][ny][nx], read only.
+ *   evecs : complex128 [nt][nt] as written by hh_eigh (unitary).
+ *   out   : complex64 [nt][ny][nx] output; must not overlap holo.  All three 16-byte aligned.
+ * Uses nx, ny, nt, k_lo, k_hi, proj_mode of *p: HH_PROJ_DIRECT sums the kept
+ * components in FP32; HH_PROJ_COMPLEMENT subtracts the dropped ones (coefficients
+ * in FP64) from H; HH_PROJ_AUTO takes the shorter list.
+ */
+hh_status hh_svd_filter(const hh_params *p, const float *holo, const double *evecs, float *out,
+                        void *stream);
 
 /*
  * Steps (a)-(e) on one stack, in the paper's order, all on `stream`.

@@ -3,6 +3,9 @@
 // Two kernels per frame group:
 //   fresnel_rows : uint16 load -> FP32 -> chirp a[m] b[n] -> row FFT -> complex64 out
 //   fresnel_cols : in-place column FFT on the row-transformed frames
+// The FP16 storage form transforms the stack's temporal mean frame once (m) and
+// then each frame minus that mean (R = H - m by linearity), and the column pass
+// writes R scaled and rounded to FP16 instead of FP32.
 // Each 1D transform is a mixed-radix Stockham FFT with 16 points per thread
 // (1024 = 16 * 16 * 4: one wave per 1024-point row, 128-byte coalesced uint16
 // loads), register DFTs, LDS exchanges between passes, and W_N twiddles from a
@@ -40,9 +43,13 @@ struct ColSlot {
   __device__ __forceinline__ int operator()(int e) const { return fft_pad(e) * W + c; }
 };
 
-template <int N, int ROWS>
+// Input of the row pass: the uint16 frames, the frames minus a float frame
+// (the stack's temporal mean), or one float frame.
+enum { kInU16 = 0, kInU16MinusMean = 1, kInF32 = 2 };
+
+template <int N, int ROWS, int IN>
 __global__ __launch_bounds__(ROWS *FftCfg<N>::T) void fresnel_rows(
-    const uint16_t *__restrict__ frames, int ny, const float2 *__restrict__ chirp_x,
+    const void *__restrict__ src, const float *__restrict__ mean, int ny, const float2 *__restrict__ chirp_x,
     const float2 *__restrict__ chirp_y, const float2 *__restrict__ tw, float2 *__restrict__ out) {
   constexpr int E = FftCfg<N>::E, T = FftCfg<N>::T;
   const int t = threadIdx.x % T;
@@ -50,6 +57,7 @@ __global__ __launch_bounds__(ROWS *FftCfg<N>::T) void fresnel_rows(
   const int row = blockIdx.x * ROWS + r;
   const bool live = row < ny;
   const size_t base = ((size_t)blockIdx.y * ny + (live ? row : 0)) * N;
+  const size_t mbase = (size_t)(live ? row : 0) * N;
 
   float2 v[E];
   {
@@ -57,7 +65,15 @@ __global__ __launch_bounds__(ROWS *FftCfg<N>::T) void fresnel_rows(
 #pragma unroll
     for (int i = 0; i < E; ++i) {
       const int m = t + T * i;
-      const float val = live ? (float)frames[base + m] : 0.0f;
+      float val = 0.0f;
+      if (live) {
+        if constexpr (IN == kInF32) {
+          val = static_cast<const float *>(src)[base + m];
+        } else {
+          val = (float)static_cast<const uint16_t *>(src)[base + m];
+          if constexpr (IN == kInU16MinusMean) val -= mean[mbase + m];
+        }
+      }
       const float2 c = cmul(chirp_x[m], cy);
       v[i] = make_float2(val * c.x, val * c.y);
     }
@@ -74,15 +90,19 @@ __global__ __launch_bounds__(ROWS *FftCfg<N>::T) void fresnel_rows(
   }
 }
 
-template <int N, int W>
+// R16: instead of writing the column FFT back in place, write it scaled by
+// `scale` and rounded to FP16 (round to nearest even) into r16 [frames][N][nx].
+template <int N, int W, bool R16>
 __global__ __launch_bounds__(W *FftCfg<N>::T) void fresnel_cols(float2 *__restrict__ data, int nx,
-                                                               const float2 *__restrict__ tw) {
+                                                               const float2 *__restrict__ tw, h2 *__restrict__ r16,
+                                                               float scale) {
   constexpr int E = FftCfg<N>::E, T = FftCfg<N>::T;
   const int c = threadIdx.x % W;
   const int t = threadIdx.x / W;
   const int col = blockIdx.x * W + c;
   const bool live = col < nx;
-  float2 *base = data + (size_t)blockIdx.y * N * nx + (live ? col : 0);
+  const size_t off = (size_t)blockIdx.y * N * nx + (live ? col : 0);
+  float2 *base = data + off;
 
   float2 v[E];
 #pragma unroll
@@ -94,80 +114,157 @@ __global__ __launch_bounds__(W *FftCfg<N>::T) void fresnel_cols(float2 *__restri
     fft_passes<N, 16, 0>(v, t, tw, (float2 *)nullptr, ColSlot<W>{c});
   }
   if (live) {
+    if constexpr (R16) {
+      h2 *ob = r16 + off;
 #pragma unroll
-    for (int i = 0; i < E; ++i) base[(size_t)(t + T * i) * nx] = v[i];
+      for (int i = 0; i < E; ++i) {
+        h2 q;
+        q.x = (_Float16)(v[i].x * scale);
+        q.y = (_Float16)(v[i].y * scale);
+        ob[(size_t)(t + T * i) * nx] = q;
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < E; ++i) base[(size_t)(t + T * i) * nx] = v[i];
+    }
   }
 }
 
+// mean[p] = (1 / nt) sum_t frames[t][p]: four pixels per thread
+__global__ __launch_bounds__(256) void frame_mean(const uint16_t *__restrict__ frames, int nt, long long npix,
+                                                  float *__restrict__ mean) {
+  const long long q = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (4 * q >= npix) return;
+  const ushort4 *f4 = reinterpret_cast<const ushort4 *>(frames);
+  const long long nq = npix / 4;
+  unsigned s0 = 0, s1 = 0, s2 = 0, s3 = 0;  // exact: nt * 65535 < 2^32
+  for (int t = 0; t < nt; ++t) {
+    const ushort4 a = f4[(long long)t * nq + q];
+    s0 += a.x;
+    s1 += a.y;
+    s2 += a.z;
+    s3 += a.w;
+  }
+  const float inv = 1.0f / (float)nt;
+  reinterpret_cast<float4 *>(mean)[q] = make_float4((float)s0 * inv, (float)s1 * inv, (float)s2 * inv, (float)s3 * inv);
+}
+
 template <int N>
-hipError_t rows_n(const Plan &pl, const uint16_t *frames, int nframes, float2 *out, hipStream_t s) {
+hipError_t rows_n(const Plan &pl, int in_mode, const void *src, const float *mean, int nframes, float2 *out,
+                  hipStream_t s) {
   constexpr int R = rows_per_wg<N>();
-  dim3 grid((pl.ny + R - 1) / R, nframes);
+  dim3 grid((pl.ny + R - 1) / R, nframes), block(R * FftCfg<N>::T);
   ProfScope ps("fresnel_rows", s);
-  hipLaunchKernelGGL((fresnel_rows<N, R>), grid, dim3(R * FftCfg<N>::T), 0, s, frames, pl.ny,
-                     pl.chirp_x, pl.chirp_y, pl.tw_x, out);
+  if (in_mode == kInU16)
+    hipLaunchKernelGGL((fresnel_rows<N, R, kInU16>), grid, block, 0, s, src, mean, pl.ny, pl.chirp_x, pl.chirp_y,
+                       pl.tw_x, out);
+  else if (in_mode == kInU16MinusMean)
+    hipLaunchKernelGGL((fresnel_rows<N, R, kInU16MinusMean>), grid, block, 0, s, src, mean, pl.ny, pl.chirp_x,
+                       pl.chirp_y, pl.tw_x, out);
+  else
+    hipLaunchKernelGGL((fresnel_rows<N, R, kInF32>), grid, block, 0, s, src, mean, pl.ny, pl.chirp_x, pl.chirp_y,
+                       pl.tw_x, out);
   return hipGetLastError();
 }
 
 template <int N>
-hipError_t cols_n(const Plan &pl, int nframes, float2 *data, hipStream_t s) {
+hipError_t cols_n(const Plan &pl, int nframes, float2 *data, h2 *r16, float scale, hipStream_t s) {
   constexpr int W = cols_per_wg<N>();
-  dim3 grid((pl.nx + W - 1) / W, nframes);
-  ProfScope ps("fresnel_cols", s);
-  hipLaunchKernelGGL((fresnel_cols<N, W>), grid, dim3(W * FftCfg<N>::T), 0, s, data, pl.nx, pl.tw_y);
+  dim3 grid((pl.nx + W - 1) / W, nframes), block(W * FftCfg<N>::T);
+  ProfScope ps(r16 ? "fresnel_cols_r16" : "fresnel_cols", s);
+  if (r16)
+    hipLaunchKernelGGL((fresnel_cols<N, W, true>), grid, block, 0, s, data, pl.nx, pl.tw_y, r16, scale);
+  else
+    hipLaunchKernelGGL((fresnel_cols<N, W, false>), grid, block, 0, s, data, pl.nx, pl.tw_y, r16, scale);
   return hipGetLastError();
 }
 
-hipError_t rows_dispatch(const Plan &pl, const uint16_t *f, int n, float2 *o, hipStream_t s) {
+hipError_t rows_dispatch(const Plan &pl, int in_mode, const void *f, const float *mean, int n, float2 *o,
+                         hipStream_t s) {
   switch (pl.nx) {
-    case 8: return rows_n<8>(pl, f, n, o, s);
-    case 16: return rows_n<16>(pl, f, n, o, s);
-    case 32: return rows_n<32>(pl, f, n, o, s);
-    case 64: return rows_n<64>(pl, f, n, o, s);
-    case 128: return rows_n<128>(pl, f, n, o, s);
-    case 256: return rows_n<256>(pl, f, n, o, s);
-    case 512: return rows_n<512>(pl, f, n, o, s);
-    case 1024: return rows_n<1024>(pl, f, n, o, s);
-    case 2048: return rows_n<2048>(pl, f, n, o, s);
-    case 4096: return rows_n<4096>(pl, f, n, o, s);
+    case 8: return rows_n<8>(pl, in_mode, f, mean, n, o, s);
+    case 16: return rows_n<16>(pl, in_mode, f, mean, n, o, s);
+    case 32: return rows_n<32>(pl, in_mode, f, mean, n, o, s);
+    case 64: return rows_n<64>(pl, in_mode, f, mean, n, o, s);
+    case 128: return rows_n<128>(pl, in_mode, f, mean, n, o, s);
+    case 256: return rows_n<256>(pl, in_mode, f, mean, n, o, s);
+    case 512: return rows_n<512>(pl, in_mode, f, mean, n, o, s);
+    case 1024: return rows_n<1024>(pl, in_mode, f, mean, n, o, s);
+    case 2048: return rows_n<2048>(pl, in_mode, f, mean, n, o, s);
+    case 4096: return rows_n<4096>(pl, in_mode, f, mean, n, o, s);
   }
   return hipErrorInvalidValue;
 }
 
-hipError_t cols_dispatch(const Plan &pl, int n, float2 *d, hipStream_t s) {
+hipError_t cols_dispatch(const Plan &pl, int n, float2 *d, h2 *r16, float scale, hipStream_t s) {
   switch (pl.ny) {
-    case 8: return cols_n<8>(pl, n, d, s);
-    case 16: return cols_n<16>(pl, n, d, s);
-    case 32: return cols_n<32>(pl, n, d, s);
-    case 64: return cols_n<64>(pl, n, d, s);
-    case 128: return cols_n<128>(pl, n, d, s);
-    case 256: return cols_n<256>(pl, n, d, s);
-    case 512: return cols_n<512>(pl, n, d, s);
-    case 1024: return cols_n<1024>(pl, n, d, s);
-    case 2048: return cols_n<2048>(pl, n, d, s);
-    case 4096: return cols_n<4096>(pl, n, d, s);
+    case 8: return cols_n<8>(pl, n, d, r16, scale, s);
+    case 16: return cols_n<16>(pl, n, d, r16, scale, s);
+    case 32: return cols_n<32>(pl, n, d, r16, scale, s);
+    case 64: return cols_n<64>(pl, n, d, r16, scale, s);
+    case 128: return cols_n<128>(pl, n, d, r16, scale, s);
+    case 256: return cols_n<256>(pl, n, d, r16, scale, s);
+    case 512: return cols_n<512>(pl, n, d, r16, scale, s);
+    case 1024: return cols_n<1024>(pl, n, d, r16, scale, s);
+    case 2048: return cols_n<2048>(pl, n, d, r16, scale, s);
+    case 4096: return cols_n<4096>(pl, n, d, r16, scale, s);
   }
   return hipErrorInvalidValue;
+}
+
+// frames per group: about 64 MiB of FP32 holograms, so that a group's
+// row-transformed frames are still in the last-level cache when the column pass
+// reads them back
+int group_frames(const Plan &pl) {
+  const size_t frame_bytes = (size_t)pl.nx * pl.ny * sizeof(float2);
+  const int g = (int)((64u << 20) / frame_bytes);
+  return g < 1 ? 1 : g;
 }
 
 }  // namespace
 
-// Frames are processed in groups so that a group's row-transformed frames are
-// still in the last-level cache when the column pass reads them back.
+int fresnel_group_frames(int nx, int ny, int nframes) {
+  const size_t frame_bytes = (size_t)nx * ny * sizeof(float2);
+  int g = (int)((64u << 20) / frame_bytes);
+  if (g < 1) g = 1;
+  return g < nframes ? g : nframes;
+}
+
 hipError_t launch_fresnel(const Plan &pl, const uint16_t *frames, int nframes, float2 *holo,
                           hipStream_t s) {
-  const size_t frame_bytes = (size_t)pl.nx * pl.ny * sizeof(float2);
-  int group = (int)((64u << 20) / frame_bytes);  // about 64 MiB of holograms per group
-  if (group < 1) group = 1;
+  const int group = group_frames(pl);
   for (int f0 = 0; f0 < nframes; f0 += group) {
     const int n = nframes - f0 < group ? nframes - f0 : group;
     const size_t off = (size_t)f0 * pl.nx * pl.ny;
-    hipError_t e = rows_dispatch(pl, frames + off, n, holo + off, s);
+    hipError_t e = rows_dispatch(pl, kInU16, frames + off, nullptr, n, holo + off, s);
     if (e != hipSuccess) return e;
-    e = cols_dispatch(pl, n, holo + off, s);
+    e = cols_dispatch(pl, n, holo + off, nullptr, 0.f, s);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
+}
+
+int fresnel_r16_group(const Plan &pl, int nframes) { return fresnel_group_frames(pl.nx, pl.ny, nframes); }
+
+hipError_t launch_fresnel_r16(const Plan &pl, const uint16_t *frames, int nframes, float *mean, float2 *m,
+                              float2 *group_buf, h2 *r16, float scale, hipStream_t s) {
+  const long long npix = (long long)pl.nx * pl.ny;
+  {
+    ProfScope ps("frame_mean", s);
+    hipLaunchKernelGGL(frame_mean, dim3((unsigned)((npix / 4 + 255) / 256)), dim3(256), 0, s, frames, nframes, npix,
+                       mean);
+  }
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess) e = rows_dispatch(pl, kInF32, mean, nullptr, 1, m, s);
+  if (e == hipSuccess) e = cols_dispatch(pl, 1, m, nullptr, 0.f, s);
+  const int group = fresnel_r16_group(pl, nframes);
+  for (int f0 = 0; f0 < nframes && e == hipSuccess; f0 += group) {
+    const int n = nframes - f0 < group ? nframes - f0 : group;
+    const size_t off = (size_t)f0 * npix;
+    e = rows_dispatch(pl, kInU16MinusMean, frames + off, mean, n, group_buf, s);
+    if (e == hipSuccess) e = cols_dispatch(pl, n, group_buf, r16 + off, scale, s);
+  }
+  return e;
 }
 
 }  // namespace hh

@@ -554,6 +554,126 @@ __global__ __launch_bounds__(256) void gram_partial_lp(const float2 *__restrict_
   }
 }
 
+
+// FP16 storage form (n_t <= 32): the stack arrives split as H = m 1^T + R with m
+// (complex64, one per pixel) and R stored as FP16(s R), s a power of two.  R^H R
+// runs on v_mfma_f32_16x16x32_f16 straight from the stored halves (no conversion),
+// unscaled by 1/s^2 exactly at the flush; the rank-one terms use m and R / s in
+// FP32 over 8 pixels, then FP64.  Lane (f, kq) holds frames f and 16 + f of the 8
+// pixels 8 kq .. 8 kq + 7 of each 32-pixel step (two 16-byte loads per frame).
+__global__ __launch_bounds__(256) void gram_partial_r16(const h2 *__restrict__ R, const float2 *__restrict__ M,
+                                                         int nt, long long npix, float inv_s,
+                                                         double *__restrict__ partial) {
+  constexpr int D = 32;
+  __shared__ double red[2 * D * D];
+  __shared__ double2 ared[4][4][D];
+  __shared__ double mmred[4][4];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int f = lane & 15, kq = lane >> 4;
+  const long long p0 = ((long long)blockIdx.x * 4 + wave) * kGramPxPerWave;
+  const bool v0 = f < nt, v1 = (16 + f) < nt;
+  const uint4 *r0p = reinterpret_cast<const uint4 *>(R + (long long)(v0 ? f : 0) * npix + p0) + 2 * kq;
+  const uint4 *r1p = reinterpret_cast<const uint4 *>(R + (long long)(v1 ? 16 + f : 0) * npix + p0) + 2 * kq;
+  const float4 *mp = reinterpret_cast<const float4 *>(M + p0) + 4 * kq;
+  union U8 {
+    uint4 q[2];
+    h2 h[8];
+  };
+
+  v4f S00 = {0.f, 0.f, 0.f, 0.f}, S01 = S00, S11 = S00, Q00 = S00, Q01 = S00, Q10 = S00, Q11 = S00;
+  double2 a0 = make_double2(0.0, 0.0), a1 = a0;
+  double mm = 0.0;
+  constexpr int STEPS = kGramPxPerWave / 32;
+  for (int j = 0; j < STEPS; ++j) {
+    const bool in = p0 + 32 * j + 8 * kq < npix;  // npix is a multiple of 8
+    U8 x0, x1;
+    float4 mq[4];
+#pragma unroll
+    for (int g = 0; g < 2; ++g) {
+      x0.q[g] = (v0 && in) ? r0p[8 * j + g] : make_uint4(0u, 0u, 0u, 0u);
+      x1.q[g] = (v1 && in) ? r1p[8 * j + g] : make_uint4(0u, 0u, 0u, 0u);
+    }
+#pragma unroll
+    for (int g = 0; g < 4; ++g) mq[g] = in ? mp[16 * j + g] : make_float4(0.f, 0.f, 0.f, 0.f);
+    v8h re0, im0, re1, im1;
+    float a0r = 0.f, a0i = 0.f, a1r = 0.f, a1i = 0.f, mmf = 0.f;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      re0[e] = x0.h[e].x;
+      im0[e] = x0.h[e].y;
+      re1[e] = x1.h[e].x;
+      im1[e] = x1.h[e].y;
+      const float mr = (e & 1) ? mq[e >> 1].z : mq[e >> 1].x;
+      const float mi = (e & 1) ? mq[e >> 1].w : mq[e >> 1].y;
+      const float r0r = (float)x0.h[e].x * inv_s, r0i = (float)x0.h[e].y * inv_s;
+      const float r1r = (float)x1.h[e].x * inv_s, r1i = (float)x1.h[e].y * inv_s;
+      mmf += mr * mr + mi * mi;
+      a0r += mr * r0r + mi * r0i;
+      a0i += mr * r0i - mi * r0r;
+      a1r += mr * r1r + mi * r1i;
+      a1i += mr * r1i - mi * r1r;
+    }
+    a0.x += a0r;
+    a0.y += a0i;
+    a1.x += a1r;
+    a1.y += a1i;
+    mm += mmf;
+    S00 = __builtin_amdgcn_mfma_f32_16x16x32_f16(re0, re0, S00, 0, 0, 0);
+    S00 = __builtin_amdgcn_mfma_f32_16x16x32_f16(im0, im0, S00, 0, 0, 0);
+    Q00 = __builtin_amdgcn_mfma_f32_16x16x32_f16(re0, im0, Q00, 0, 0, 0);
+    S01 = __builtin_amdgcn_mfma_f32_16x16x32_f16(re0, re1, S01, 0, 0, 0);
+    S01 = __builtin_amdgcn_mfma_f32_16x16x32_f16(im0, im1, S01, 0, 0, 0);
+    S11 = __builtin_amdgcn_mfma_f32_16x16x32_f16(re1, re1, S11, 0, 0, 0);
+    S11 = __builtin_amdgcn_mfma_f32_16x16x32_f16(im1, im1, S11, 0, 0, 0);
+    Q01 = __builtin_amdgcn_mfma_f32_16x16x32_f16(re0, im1, Q01, 0, 0, 0);
+    Q10 = __builtin_amdgcn_mfma_f32_16x16x32_f16(re1, im0, Q10, 0, 0, 0);
+    Q11 = __builtin_amdgcn_mfma_f32_16x16x32_f16(re1, im1, Q11, 0, 0, 0);
+  }
+
+  const double un = (double)inv_s * (double)inv_s;
+  for (int i = tid; i < 2 * D * D; i += 256) red[i] = 0.0;
+  ared[wave][kq][f] = a0;
+  ared[wave][kq][16 + f] = a1;
+  if (f == 0) mmred[wave][kq] = mm;
+  __syncthreads();
+  for (int w = 0; w < 4; ++w) {
+    if (wave == w) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = 4 * kq + r, jj = f;  // 16x16 accumulator layout
+        red[i * D + jj] += (double)S00[r] * un;
+        red[D * D + i * D + jj] += (double)Q00[r] * un;
+        red[i * D + 16 + jj] += (double)S01[r] * un;
+        red[(16 + i) * D + 16 + jj] += (double)S11[r] * un;
+        red[D * D + i * D + 16 + jj] += (double)Q01[r] * un;
+        red[D * D + (16 + i) * D + jj] += (double)Q10[r] * un;
+        red[D * D + (16 + i) * D + 16 + jj] += (double)Q11[r] * un;
+      }
+    }
+    __syncthreads();
+  }
+  double *out = partial + (size_t)blockIdx.x * partial_len(D);
+  for (int i = tid; i < 2 * D * D; i += 256) out[i] = red[i];
+  if (tid < D) {
+    double ar = 0.0, ai = 0.0;
+    for (int w = 0; w < 4; ++w)
+      for (int q = 0; q < 4; ++q) {
+        ar += ared[w][q][tid].x;
+        ai += ared[w][q][tid].y;
+      }
+    out[2 * D * D + tid] = ar;
+    out[2 * D * D + D + tid] = ai;
+  }
+  if (tid == 0) {
+    double t = 0.0;
+    for (int w = 0; w < 4; ++w)
+      for (int q = 0; q < 4; ++q) t += mmred[w][q];
+    out[2 * D * D + 2 * D] = t;
+    out[2 * D * D + 2 * D + 1] = 0.0;
+  }
+}
+
 // out[g2][l] = sum over g in segment g2 of in[g][l], segments in increasing g.
 __global__ __launch_bounds__(256) void gram_reduce(const double *__restrict__ in, int G, int L, int G2,
                                                    double *__restrict__ out) {
@@ -606,6 +726,10 @@ GramLayout gram_layout(int nt, long long npix) {
   return L;
 }
 
+namespace {
+hipError_t gram_tail(const GramLayout &L, int nt, double *partial, double *partial2, double *cov, hipStream_t s);
+}
+
 hipError_t launch_gram(const GramLayout &L, const float2 *holo, int nt, long long npix, double *partial,
                        double *partial2, double *cov, hipStream_t s, int precision) {
   if (precision != HH_FP32 && nt <= 32) {
@@ -627,8 +751,26 @@ hipError_t launch_gram(const GramLayout &L, const float2 *holo, int nt, long lon
     else
       hipLaunchKernelGGL(gram_partial64, dim3(L.groups), dim3(256), 0, s, holo, nt, npix, partial);
   }
-  hipError_t e = hipGetLastError();
+  const hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
+  return gram_tail(L, nt, partial, partial2, cov, s);
+}
+
+hipError_t launch_gram_r16(const GramLayout &L, const h2 *r16, const float2 *m, int nt, long long npix, float inv_s,
+                           double *partial, double *partial2, double *cov, hipStream_t s) {
+  {
+    ProfScope ps("gram_partial_r16", s);
+    hipLaunchKernelGGL(gram_partial_r16, dim3(L.groups), dim3(256), 0, s, r16, m, nt, npix, inv_s, partial);
+  }
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return gram_tail(L, nt, partial, partial2, cov, s);
+}
+
+namespace {
+// fixed-order reduction of the workgroup partials and Hermitian assembly
+hipError_t gram_tail(const GramLayout &L, int nt, double *partial, double *partial2, double *cov, hipStream_t s) {
+  hipError_t e;
   const int Lw = partial_len(L.D);
   {
     ProfScope ps("gram_reduce", s);
@@ -644,5 +786,6 @@ hipError_t launch_gram(const GramLayout &L, const float2 *holo, int nt, long lon
   }
   return hipGetLastError();
 }
+}  // namespace
 
 }  // namespace hh

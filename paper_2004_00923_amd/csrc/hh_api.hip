@@ -211,10 +211,15 @@ hh_status check_select(const hh_params *p) {
   return HH_OK;
 }
 
-hh_status check_precision(const hh_params *p) {
-  if (p->precision < HH_FP32 || p->precision > HH_FP8E4M3) return fail(HH_E_INVALID, "precision=%d unknown", p->precision);
+// from_frames: the entry point starts from frames (hh_pipeline and the batched
+// forms); the FP16 storage form exists only there.
+hh_status check_precision(const hh_params *p, bool from_frames) {
+  if (p->precision < HH_FP32 || p->precision > HH_FP16_STORE)
+    return fail(HH_E_INVALID, "precision=%d unknown", p->precision);
   if (p->precision != HH_FP32 && p->nt > 32)
     return fail(HH_E_UNSUPPORTED, "precision form %d is built for nt <= 32 (nt=%d)", p->precision, p->nt);
+  if (p->precision == HH_FP16_STORE && !from_frames)
+    return fail(HH_E_UNSUPPORTED, "HH_FP16_STORE applies to entry points that start from frames");
   return HH_OK;
 }
 
@@ -222,7 +227,9 @@ bool aligned(const void *ptr, size_t a) { return ((uintptr_t)ptr % a) == 0; }
 
 struct PipeLayout {
   GramLayout g;
-  size_t holo = 0, part = 0, part2 = 0, cov = 0, evals = 0, evecs = 0, info = 0, total = 0;
+  bool r16 = false;  // FP16 storage form
+  size_t holo = 0, r16buf = 0, group = 0, mean = 0, m = 0;
+  size_t part = 0, part2 = 0, cov = 0, evals = 0, evecs = 0, info = 0, total = 0;
 };
 
 // with_holo = false: the layout of steps (b)-(e) on a hologram stack the caller holds
@@ -230,9 +237,17 @@ PipeLayout pipe_layout(const hh_params *p, bool with_holo = true) {
   PipeLayout L;
   const long long npix = (long long)p->nx * p->ny;
   L.g = gram_layout(p->nt, npix);
+  L.r16 = with_holo && p->precision == HH_FP16_STORE;
   size_t o = 0;
-  L.holo = o;
-  if (with_holo) o = align_up(o + (size_t)p->nt * npix * sizeof(float2));
+  if (L.r16) {
+    L.r16buf = o; o = align_up(o + (size_t)p->nt * npix * sizeof(h2));
+    L.group = o; o = align_up(o + (size_t)fresnel_group_frames(p->nx, p->ny, p->nt) * npix * sizeof(float2));
+    L.mean = o; o = align_up(o + (size_t)npix * sizeof(float));
+    L.m = o; o = align_up(o + (size_t)npix * sizeof(float2));
+  } else {
+    L.holo = o;
+    if (with_holo) o = align_up(o + (size_t)p->nt * npix * sizeof(float2));
+  }
   L.part = o; o = align_up(o + L.g.partial_bytes);
   L.part2 = o; o = align_up(o + L.g.partial2_bytes);
   L.cov = o; o = align_up(o + (size_t)p->nt * p->nt * 2 * sizeof(double));
@@ -241,6 +256,57 @@ PipeLayout pipe_layout(const hh_params *p, bool with_holo = true) {
   L.info = o; o = align_up(o + sizeof(int));
   L.total = o;
   return L;
+}
+
+// Power-of-two scale of the stored FP16 residual: |frame - mean| <= 65535, so
+// |R[p]| <= npix * 65535 and npix * 65535 * s stays below the FP16 maximum 65504.
+float r16_inv_scale(long long npix) {
+  int e = 1;
+  while ((1ll << (e - 1)) < npix) ++e;  // 2^(e-1) >= npix, npix a power of two
+  return std::ldexp(1.0f, e);             // 1 / s = 2 npix
+}
+
+// Steps (a)+(b) of one stack in its workspace region (frames given), or step (b)
+// on the caller's hologram (holo given).  Fills the views that steps (d)+(e) read.
+struct StackViews {
+  const float2 *H = nullptr;
+  const h2 *r16 = nullptr;
+  const float2 *m = nullptr;
+  float inv_s = 1.f;
+  double *cov = nullptr;
+};
+
+hipError_t enqueue_front(const hh_params &p, const Plan *pl, const PipeLayout &L, char *ws, const uint16_t *frames,
+                         const float2 *holo, StackViews &v, hipStream_t s) {
+  const long long npix = (long long)p.nx * p.ny;
+  double *part = reinterpret_cast<double *>(ws + L.part), *part2 = reinterpret_cast<double *>(ws + L.part2);
+  v.cov = reinterpret_cast<double *>(ws + L.cov);
+  if (L.r16) {
+    h2 *r = reinterpret_cast<h2 *>(ws + L.r16buf);
+    float2 *m = reinterpret_cast<float2 *>(ws + L.m);
+    v.inv_s = r16_inv_scale(npix);
+    v.r16 = r;
+    v.m = m;
+    hipError_t e = launch_fresnel_r16(*pl, frames, p.nt, reinterpret_cast<float *>(ws + L.mean), m,
+                                      reinterpret_cast<float2 *>(ws + L.group), r, 1.0f / v.inv_s, s);
+    if (e != hipSuccess) return e;
+    return launch_gram_r16(L.g, r, m, p.nt, npix, v.inv_s, part, part2, v.cov, s);
+  }
+  if (frames) {
+    float2 *H = reinterpret_cast<float2 *>(ws + L.holo);
+    hipError_t e = launch_fresnel(*pl, frames, p.nt, H, s);
+    if (e != hipSuccess) return e;
+    v.H = H;
+  } else {
+    v.H = holo;
+  }
+  return launch_gram(L.g, v.H, p.nt, npix, part, part2, v.cov, s, p.precision);
+}
+
+hipError_t enqueue_back(const hh_params &p, const StackViews &v, const double *V, float *image, hipStream_t s) {
+  const long long npix = (long long)p.nx * p.ny;
+  if (v.r16) return launch_project_r16(v.r16, v.m, v.inv_s, p.nt, npix, V, p.k_lo, p.k_hi, p.proj_mode, image, s);
+  return launch_project(v.H, p.nt, npix, V, p.k_lo, p.k_hi, p.proj_mode, image, s);
 }
 
 constexpr int kMaxBatch = 4096;
@@ -274,12 +340,13 @@ hh_status run_batch(const hh_params *p, int n, const BatchItem *it, void *worksp
   for (int i = 0; i < n; ++i) {
     hh_status st;
     if ((with_holo && (st = check_optics(p + i))) || (st = check_stack(p + i)) || (st = check_select(p + i)) ||
-        (st = check_precision(p + i))) {
+        (st = check_precision(p + i, with_holo))) {
       const std::string msg = g_err;
       return fail(st, "stack %d: %s", i, msg.c_str());
     }
     if (!it[i].image) return fail(HH_E_INVALID, "stack %d: image must be non-NULL", i);
-    if (!aligned(it[i].image, 8) || (it[i].evals && !aligned(it[i].evals, 8)) ||
+    if ((it[i].frames && !aligned(it[i].frames, p[i].precision == HH_FP16_STORE ? 8 : 2)) ||
+        !aligned(it[i].image, 8) || (it[i].evals && !aligned(it[i].evals, 8)) ||
         (it[i].evecs && !aligned(it[i].evecs, 16)) || (it[i].info && !aligned(it[i].info, 4)))
       return fail(HH_E_INVALID, "stack %d: arrays misaligned", i);
     need += align_up(pipe_layout(p + i, with_holo).total);
@@ -291,32 +358,20 @@ hh_status run_batch(const hh_params *p, int n, const BatchItem *it, void *worksp
     for (int i = 0; i < n; ++i)
       if (!(plans[i] = get_plan(p[i]))) return HH_E_DEVICE;
   std::vector<EighProblem> probs(n);
-  std::vector<const float2 *> H(n);
+  std::vector<StackViews> views(n);
   char *ws = static_cast<char *>(workspace);
   hipError_t e = hipSuccess;
   for (int i = 0; i < n && e == hipSuccess; ++i) {
     const PipeLayout L = pipe_layout(p + i, with_holo);
-    const long long npix = (long long)p[i].nx * p[i].ny;
-    double *cov = reinterpret_cast<double *>(ws + L.cov);
-    if (with_holo) {
-      float2 *Hw = reinterpret_cast<float2 *>(ws + L.holo);
-      e = launch_fresnel(*plans[i], it[i].frames, p[i].nt, Hw, s);
-      H[i] = Hw;
-    } else {
-      H[i] = it[i].holo;
-    }
-    if (e == hipSuccess)
-      e = launch_gram(L.g, H[i], p[i].nt, npix, reinterpret_cast<double *>(ws + L.part),
-                      reinterpret_cast<double *>(ws + L.part2), cov, s, p[i].precision);
-    probs[i] = EighProblem{p[i].nt, cov, it[i].evals ? it[i].evals : reinterpret_cast<double *>(ws + L.evals),
+    e = enqueue_front(p[i], plans[i], L, ws, it[i].frames, it[i].holo, views[i], s);
+    probs[i] = EighProblem{p[i].nt, views[i].cov,
+                           it[i].evals ? it[i].evals : reinterpret_cast<double *>(ws + L.evals),
                            it[i].evecs ? it[i].evecs : reinterpret_cast<double *>(ws + L.evecs),
                            it[i].info ? it[i].info : reinterpret_cast<int *>(ws + L.info)};
     ws += align_up(L.total);
   }
   if (e == hipSuccess) e = launch_eigh_batch(probs.data(), n, 40, s);
-  for (int i = 0; i < n && e == hipSuccess; ++i)
-    e = launch_project(H[i], p[i].nt, (long long)p[i].nx * p[i].ny, probs[i].evecs, p[i].k_lo, p[i].k_hi,
-                       p[i].proj_mode, it[i].image, s);
+  for (int i = 0; i < n && e == hipSuccess; ++i) e = enqueue_back(p[i], views[i], probs[i].evecs, it[i].image, s);
   if (e != hipSuccess) return device_fail(e, who);
   return HH_OK;
 }
@@ -374,7 +429,7 @@ hh_status hh_fresnel(const hh_params *p, const uint16_t *frames, int32_t nframes
 hh_status hh_covariance(const hh_params *p, const float *holo, double *cov, void *workspace, size_t ws_bytes,
                         void *stream) {
   hh_status st;
-  if ((st = check_stack(p)) || (st = check_precision(p))) return st;
+  if ((st = check_stack(p)) || (st = check_precision(p, false))) return st;
   if (!holo || !cov) return fail(HH_E_INVALID, "holo and cov must be non-NULL");
   if (!aligned(holo, 16) || !aligned(cov, 16)) return fail(HH_E_INVALID, "holo/cov misaligned");
   const size_t need = cov_ws_bytes(p);
@@ -406,9 +461,25 @@ hh_status hh_eigh(int32_t nt, const double *cov, double *evals, double *evecs, i
   return hh_eigh_ex(nt, cov, evals, evecs, info, 40, stream);
 }
 
+hh_status hh_svd_filter(const hh_params *p, const float *holo, const double *evecs, float *out, void *stream) {
+  hh_status st;
+  if ((st = check_stack(p)) || (st = check_select(p))) return st;
+  if (!holo || !evecs || !out) return fail(HH_E_INVALID, "holo, evecs, out must be non-NULL");
+  if (!aligned(holo, 16) || !aligned(evecs, 16) || !aligned(out, 16))
+    return fail(HH_E_INVALID, "holo/evecs/out must be 16-byte aligned");
+  const size_t bytes = (size_t)p->nt * p->nx * p->ny * sizeof(float2);
+  const char *h0 = reinterpret_cast<const char *>(holo), *o0 = reinterpret_cast<const char *>(out);
+  if (h0 < o0 + bytes && o0 < h0 + bytes) return fail(HH_E_INVALID, "out must not overlap holo");
+  hipError_t e = launch_svd_filter(reinterpret_cast<const float2 *>(holo), p->nt, (long long)p->nx * p->ny, evecs,
+                                   p->k_lo, p->k_hi, p->proj_mode, reinterpret_cast<float2 *>(out),
+                                   (hipStream_t)stream);
+  if (e != hipSuccess) return device_fail(e, "hh_svd_filter");
+  return HH_OK;
+}
+
 hh_status hh_project_render(const hh_params *p, const float *holo, const double *evecs, float *image, void *stream) {
   hh_status st;
-  if ((st = check_stack(p)) || (st = check_select(p)) || (st = check_precision(p))) return st;
+  if ((st = check_stack(p)) || (st = check_select(p)) || (st = check_precision(p, false))) return st;
   if (!holo || !evecs || !image) return fail(HH_E_INVALID, "holo, evecs, image must be non-NULL");
   if (!aligned(holo, 16) || !aligned(evecs, 16) || !aligned(image, 8))
     return fail(HH_E_INVALID, "holo/evecs/image misaligned");
@@ -434,11 +505,11 @@ hh_status hh_fourier_render(const hh_params *p, const float *holo, float *image,
 hh_status hh_pipeline(const hh_params *p, const uint16_t *frames, float *image, double *evals, double *evecs,
                       int32_t *info, void *workspace, size_t ws_bytes, void *stream) {
   hh_status st;
-  if ((st = check_optics(p)) || (st = check_stack(p)) || (st = check_select(p)) || (st = check_precision(p)))
+  if ((st = check_optics(p)) || (st = check_stack(p)) || (st = check_select(p)) || (st = check_precision(p, true)))
     return st;
   if (!frames || !image) return fail(HH_E_INVALID, "frames and image must be non-NULL");
-  if (!aligned(frames, 2) || !aligned(image, 8) || (evals && !aligned(evals, 8)) || (evecs && !aligned(evecs, 16)) ||
-      (info && !aligned(info, 4)))
+  if (!aligned(frames, p->precision == HH_FP16_STORE ? 8 : 2) || !aligned(image, 8) || (evals && !aligned(evals, 8)) ||
+      (evecs && !aligned(evecs, 16)) || (info && !aligned(info, 4)))
     return fail(HH_E_INVALID, "pipeline arrays misaligned");
   const PipeLayout L = pipe_layout(p);
   if (!workspace || ws_bytes < L.total || !aligned(workspace, 256))
@@ -446,19 +517,14 @@ hh_status hh_pipeline(const hh_params *p, const uint16_t *frames, float *image, 
   const Plan *pl = get_plan(*p);
   if (!pl) return HH_E_DEVICE;
   char *ws = static_cast<char *>(workspace);
-  float2 *H = reinterpret_cast<float2 *>(ws + L.holo);
-  double *cov = reinterpret_cast<double *>(ws + L.cov);
   double *ev = evals ? evals : reinterpret_cast<double *>(ws + L.evals);
   double *V = evecs ? evecs : reinterpret_cast<double *>(ws + L.evecs);
   int *inf = info ? info : reinterpret_cast<int *>(ws + L.info);
-  const long long npix = (long long)p->nx * p->ny;
   hipStream_t s = (hipStream_t)stream;
-  hipError_t e = launch_fresnel(*pl, frames, p->nt, H, s);
-  if (e == hipSuccess)
-    e = launch_gram(L.g, H, p->nt, npix, reinterpret_cast<double *>(ws + L.part),
-                    reinterpret_cast<double *>(ws + L.part2), cov, s, p->precision);
-  if (e == hipSuccess) e = launch_eigh(p->nt, cov, ev, V, inf, 40, s);
-  if (e == hipSuccess) e = launch_project(H, p->nt, npix, V, p->k_lo, p->k_hi, p->proj_mode, image, s);
+  StackViews v;
+  hipError_t e = enqueue_front(*p, pl, L, ws, frames, nullptr, v, s);
+  if (e == hipSuccess) e = launch_eigh(p->nt, v.cov, ev, V, inf, 40, s);
+  if (e == hipSuccess) e = enqueue_back(*p, v, V, image, s);
   if (e != hipSuccess) return device_fail(e, "hh_pipeline");
   return HH_OK;
 }

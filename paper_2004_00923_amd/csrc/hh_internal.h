@@ -42,6 +42,14 @@ struct ProfScope {
 // Step (a): row pass (uint16 -> chirp -> row FFT) then in-place column FFT.
 hipError_t launch_fresnel(const Plan &pl, const uint16_t *frames, int nframes, float2 *holo,
                           hipStream_t s);
+// FP16 storage form of step (a): mean[p] = temporal mean of the frames (float),
+// m = Fresnel(mean) (complex64), r16[t] = FP16(scale * Fresnel(frame_t - mean)).
+// group_buf holds fresnel_r16_group(pl, nframes) FP32 frames.
+typedef _Float16 h2 __attribute__((ext_vector_type(2)));
+int fresnel_r16_group(const Plan &pl, int nframes);
+int fresnel_group_frames(int nx, int ny, int nframes);
+hipError_t launch_fresnel_r16(const Plan &pl, const uint16_t *frames, int nframes, float *mean, float2 *m,
+                              float2 *group_buf, h2 *r16, float scale, hipStream_t s);
 
 // Step (b): split-K Gram partials, fixed-order reduction, Hermitian assembly.
 struct GramLayout {
@@ -58,6 +66,9 @@ GramLayout gram_layout(int nt, long long npix);
 // larger stacks use the FP32 form).
 hipError_t launch_gram(const GramLayout &L, const float2 *holo, int nt, long long npix,
                        double *partial, double *partial2, double *cov, hipStream_t s, int precision = HH_FP32);
+// FP16 storage form: H = m 1^T + r16 / s with inv_s = 1 / s (n_t <= 32).
+hipError_t launch_gram_r16(const GramLayout &L, const h2 *r16, const float2 *m, int nt, long long npix, float inv_s,
+                           double *partial, double *partial2, double *cov, hipStream_t s);
 
 // Step (c): one workgroup per problem; problems are passed by value (kernel argument).
 struct EighProblem {
@@ -78,6 +89,12 @@ hipError_t launch_eigh_batch(const EighProblem *probs, int count, int max_sweeps
 // Steps (d)+(e)
 hipError_t launch_project(const float2 *holo, int nt, long long npix, const double *V, int k_lo,
                           int k_hi, int mode, float *image, hipStream_t s);
+// FP16 storage form of steps (d)+(e): H = m + r16 * inv_s
+hipError_t launch_project_r16(const h2 *r16, const float2 *m, float inv_s, int nt, long long npix, const double *V,
+                              int k_lo, int k_hi, int mode, float *image, hipStream_t s);
+// SVD-filtered stack, Eq. (3)
+hipError_t launch_svd_filter(const float2 *holo, int nt, long long npix, const double *V, int k_lo, int k_hi,
+                             int mode, float2 *out, hipStream_t s);
 
 inline size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
 

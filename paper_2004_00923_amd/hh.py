@@ -16,11 +16,11 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libhh.so")
 
 HH_OK, HH_E_INVALID, HH_E_UNSUPPORTED, HH_E_WORKSPACE, HH_E_DEVICE, HH_E_NOT_CONVERGED = range(6)
-HH_FP32, HH_BF16, HH_FP16, HH_BF16X3, HH_FP16X3, HH_FP8E4M3 = range(6)
+HH_FP32, HH_BF16, HH_FP16, HH_BF16X3, HH_FP16X3, HH_FP8E4M3, HH_FP16_STORE = range(7)
 HH_PROJ_AUTO, HH_PROJ_DIRECT, HH_PROJ_COMPLEMENT = range(3)
 
 PRECISIONS = {"fp32": HH_FP32, "bf16": HH_BF16, "fp16": HH_FP16, "bf16x3": HH_BF16X3,
-              "fp16x3": HH_FP16X3, "fp8e4m3": HH_FP8E4M3}
+              "fp16x3": HH_FP16X3, "fp8e4m3": HH_FP8E4M3, "fp16store": HH_FP16_STORE}
 
 
 class hh_params(ctypes.Structure):
@@ -88,6 +88,7 @@ SIGNATURES = {
     "hh_project_render": (ctypes.c_int32, [ctypes.POINTER(hh_params), _P, _P, _P, _P]),
     "hh_pipeline": (ctypes.c_int32, [ctypes.POINTER(hh_params), _P, _P, _P, _P, _P, _P, ctypes.c_size_t, _P]),
     "hh_fourier_render": (ctypes.c_int32, [ctypes.POINTER(hh_params), _P, _P, _P]),
+    "hh_svd_filter": (ctypes.c_int32, [ctypes.POINTER(hh_params), _P, _P, _P, _P]),
     "hh_batch_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(hh_params), ctypes.c_int32]),
     "hh_pipeline_batch": (ctypes.c_int32, [ctypes.POINTER(hh_params), ctypes.c_int32, ctypes.POINTER(hh_stack), _P,
                                            ctypes.c_size_t, _P]),
@@ -202,6 +203,16 @@ def hh_project_render(p: Params, holo, evecs, image, stream=None):
     _dev_tensor(image, torch.float32, (p.ny, p.nx), "image")
     _check(lib().hh_project_render(ctypes.byref(p.c()), _ptr(holo), _ptr(evecs), _ptr(image), _stream(stream)))
     return image
+
+
+def hh_svd_filter(p: Params, holo, evecs, out, stream=None):
+    """Eq. (3): the stack with the dropped components removed; see include/hh.h."""
+    import torch
+    _dev_tensor(holo, torch.complex64, (p.nt, p.ny, p.nx), "holo")
+    _dev_tensor(evecs, torch.complex128, (p.nt, p.nt), "evecs")
+    _dev_tensor(out, torch.complex64, (p.nt, p.ny, p.nx), "out")
+    _check(lib().hh_svd_filter(ctypes.byref(p.c()), _ptr(holo), _ptr(evecs), _ptr(out), _stream(stream)))
+    return out
 
 
 def hh_fourier_render(p: Params, holo, image, stream=None):

@@ -266,6 +266,12 @@ def pin_project(o, frames=None, k_lo=2, k_hi=None):
     Hf = o.svd_filter_ref(H, V, k_lo, k_hi)
     e = _rel(np.sum(np.abs(Hf) ** 2, axis=0), M)
     _check(fails, "filtered-stack power = image", e <= 1e-10, f"{e:.2e}")
+    # Eq. (3) literally: U Delta I_f W^H from the library SVD of the space-time matrix
+    # (Eq. (2)); singular values come in descending order, as the kept range counts
+    Uh, dh, Whh = np.linalg.svd(o.space_time_matrix(H), full_matrices=False)
+    Hs = ((Uh[:, k_lo:k_hi + 1] * dh[k_lo:k_hi + 1]) @ Whh[k_lo:k_hi + 1, :]).T.reshape(H.shape)
+    e = _rel(Hf, Hs)
+    _check(fails, "filtered stack = U Delta I_f V^H (SVD route)", e <= 1e-9, f"{e:.2e}")
     # 8. pure-Python brute force of Eqs. (6)-(7) on a tiny stack
     Ht = H[:3, :2, :2]
     Vt = V[:3, :3]

@@ -94,14 +94,36 @@ def test_workspace_sizes():
     assert st == hh.HH_E_WORKSPACE
 
 
-def test_unbuilt_precision_forms_are_reported():
+def test_precision_form_validation():
     L = hh.lib()
     for prec in (hh.HH_BF16, hh.HH_FP16, hh.HH_BF16X3, hh.HH_FP16X3, hh.HH_FP8E4M3):
         p = hh.Params(nx=64, ny=64, nt=8, k_lo=1, k_hi=7, precision=prec).c()
-        # a 1-byte workspace stops any call that passes the precision check before device work
+        # a 1-byte workspace stops a call that passes the precision check before device work
         st = L.hh_covariance(ctypes.byref(p), ctypes.c_void_p(16), ctypes.c_void_p(16), ctypes.c_void_p(256),
                              1, None)
-        assert st in (hh.HH_E_WORKSPACE, hh.HH_E_UNSUPPORTED)
+        assert st == hh.HH_E_WORKSPACE
+        # low-precision forms are built for stacks of at most 32 frames
+        p = hh.Params(nx=64, ny=64, nt=33, k_lo=1, k_hi=7, precision=prec).c()
+        st = L.hh_covariance(ctypes.byref(p), ctypes.c_void_p(16), ctypes.c_void_p(16), ctypes.c_void_p(256),
+                             1, None)
+        assert st == hh.HH_E_UNSUPPORTED
+    # the FP16 storage form starts from frames: entry points taking FP32 holograms reject it
+    p = hh.Params(nx=64, ny=64, nt=8, k_lo=1, k_hi=7, precision=hh.HH_FP16_STORE).c()
+    assert L.hh_covariance(ctypes.byref(p), ctypes.c_void_p(16), ctypes.c_void_p(16), ctypes.c_void_p(256),
+                           1, None) == hh.HH_E_UNSUPPORTED
+    assert L.hh_project_render(ctypes.byref(p), ctypes.c_void_p(16), ctypes.c_void_p(16), ctypes.c_void_p(16),
+                               None) == hh.HH_E_UNSUPPORTED
+    st = L.hh_pipeline(ctypes.byref(p), ctypes.c_void_p(16), ctypes.c_void_p(16), None, None, None,
+                       ctypes.c_void_p(256), 1, None)
+    assert st == hh.HH_E_WORKSPACE
+    # and its frames must be 8-byte aligned
+    st = L.hh_pipeline(ctypes.byref(p), ctypes.c_void_p(18), ctypes.c_void_p(16), None, None, None,
+                       ctypes.c_void_p(256), 1, None)
+    assert st == hh.HH_E_INVALID
+    # the storage form needs less workspace than the FP32 hologram
+    a = hh.workspace_bytes(hh.Params(nx=1024, ny=1024, nt=32, k_lo=2, k_hi=31))
+    b = hh.workspace_bytes(hh.Params(nx=1024, ny=1024, nt=32, k_lo=2, k_hi=31, precision=hh.HH_FP16_STORE))
+    assert b < a
     p = hh.Params(nx=64, ny=64, nt=8, k_lo=1, k_hi=7, precision=99).c()
     assert L.hh_covariance(ctypes.byref(p), ctypes.c_void_p(16), ctypes.c_void_p(16), ctypes.c_void_p(256),
                            1, None) == hh.HH_E_INVALID

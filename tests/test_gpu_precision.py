@@ -19,6 +19,7 @@ FORMS = {
     "fp16": ("HH_FP16", 1e-2),
     "bf16": ("HH_BF16", 5e-2),
     "fp8e4m3": ("HH_FP8E4M3", 5e-1),
+    "fp16store": ("HH_FP16_STORE", 1e-3),
 }
 
 
@@ -66,7 +67,7 @@ def test_precision_table(hh, ny, nx, seed):
         M, w = _run(hh, f, 2, 31, prec)
         e_img = rel(M, r["image"])
         e_lam = float(np.abs(w - r["evals"]).max() / r["evals"][0])
-        e_c = rel(_cov(hh, H32, prec), C_ref)
+        e_c = rel(_cov(hh, H32, prec), C_ref) if prec != hh.HH_FP16_STORE else float("nan")
         say(f"{name:>8} {e_img:10.2e} {e_lam:10.2e} {e_c:10.2e}")
         if not (np.isfinite(M).all() and e_img <= bound):
             bad.append((name, e_img, bound))
@@ -100,3 +101,34 @@ def test_precision_degenerate_inputs(hh, attr):
     r = oracle.pipeline_ref(f, LAM, Z, PITCH, 2, 31)
     assert np.isfinite(M).all()
     assert np.abs(w - r["evals"]).max() <= 5e-2 * r["evals"][0]
+
+
+@pytest.mark.parametrize("nt,ny,nx,k_lo", [(32, 128, 128, 2), (16, 64, 64, 2), (3, 8, 8, 1), (32, 64, 128, 12),
+                                          (31, 32, 32, 2), (32, 1024, 1024, 3)])
+def test_fp16_store_pipeline(hh, nt, ny, nx, k_lo):
+    # the FP16 storage form within the mixed-precision bar, on several shapes
+    f = gen_stack(nt + ny + 7, nt, ny, nx)
+    M, w = _run(hh, f, k_lo, nt - 1, hh.HH_FP16_STORE)
+    r = oracle.pipeline_ref(f, LAM, Z, PITCH, k_lo, nt - 1)
+    e = rel(M, r["image"])
+    e_lam = float(np.abs(w - r["evals"]).max() / r["evals"][0])
+    say(f"fp16store {nt}x{ny}x{nx} PCs {k_lo}..{nt - 1}: image {e:.2e} lambda {e_lam:.2e}")
+    assert e <= 1e-3
+    assert e_lam <= 1e-5
+
+
+def test_fp16_store_batch_mixed_forms_equal_alone(hh):
+    import torch
+    specs = [(32, 64, 64, hh.HH_FP16_STORE), (16, 32, 128, hh.HH_FP32), (32, 128, 128, hh.HH_FP16_STORE)]
+    ps, frames, imgs, host = [], [], [], []
+    for i, (nt, ny, nx, prec) in enumerate(specs):
+        f = gen_stack(400 + i, nt, ny, nx)
+        host.append(f)
+        ps.append(hh.Params(nx=nx, ny=ny, nt=nt, k_lo=2, k_hi=nt - 1, precision=prec))
+        frames.append(to_dev(f))
+        imgs.append(torch.empty((ny, nx), dtype=torch.float32, device="cuda"))
+    ws = hh.alloc_workspace(hh.batch_workspace_bytes(ps))
+    hh.hh_pipeline_batch(ps, frames, imgs, ws)
+    for i, (nt, ny, nx, prec) in enumerate(specs):
+        alone = _run(hh, host[i], 2, nt - 1, prec)[0]
+        assert np.array_equal(to_np(imgs[i]), alone), f"stack {i}"
