@@ -264,6 +264,46 @@ hh_status hh_graph_launch(hh_graph *g, void *stream);
 void hh_graph_destroy(hh_graph *g);
 
 /*
+ * Launch choices for one problem shape.  The results do not depend on them
+ * beyond rounding (every choice meets the same accuracy bar); only speed does.
+ *   fft_rows : row-FFT launch shape: 0 = 16 points per thread, 256-thread groups;
+ *              1 = 32 points per thread, 256-thread groups; 2 = 32 points per
+ *              thread, 2 rows per group; 3 = 16 points per thread, one row per
+ *              group.  Shapes 1-3 exist for nx >= 512.
+ *   fft_cols : column-FFT launch shape: 0 = 16 points per thread, 16 columns per
+ *              group (fewer where the LDS does not hold them); 1 = 16 points, half
+ *              as many columns; 2 = 32 points per thread.  Shapes 1-2 exist for
+ *              ny >= 512.
+ *   gram_pxw : covariance split-K chunk, pixels per wavefront: 256, 512 or 1024
+ *              (FP32 partial sums grow with it).
+ *   group    : frames per Fresnel group (row pass then column pass), 0 = about
+ *              64 MiB of FP32 holograms, at most that.
+ * The FFT choices and the group apply to every call with the same (nx, ny) on
+ * the current device, gram_pxw to the same (nx * ny, nt, precision).
+ */
+typedef struct {
+  int32_t fft_rows, fft_cols, gram_pxw, group;
+} hh_tuning;
+
+/* Choices now in force for *p (defaults where none were set).  Uses nx, ny, nt, precision. */
+hh_status hh_tuning_get(const hh_params *p, hh_tuning *t);
+/* Sets the choices for the shape of *p (validated; HH_E_INVALID if out of range). */
+hh_status hh_tuning_set(const hh_params *p, const hh_tuning *t);
+/* Forgets every choice (back to the defaults). */
+void hh_tuning_reset(void);
+
+/*
+ * Autotuner: times hh_pipeline on `frames` (reps timed runs per candidate, the
+ * median kept) for each launch choice in turn (row shape, column shape, group,
+ * split-K chunk, each keeping the best so far), stores the fastest for the shape
+ * of *p and returns it in *best (may be NULL).  Synchronous: it waits for its
+ * own launches on `stream`, allocates a scratch image, and must not be called
+ * under stream capture.  workspace as for hh_pipeline.  1 <= reps <= 1000.
+ */
+hh_status hh_autotune(const hh_params *p, const uint16_t *frames, void *workspace, size_t ws_bytes,
+                      int32_t reps, hh_tuning *best, void *stream);
+
+/*
  * Fourier demodulation, Eqs. (8)-(9) (the paper's comparison method):
  *   image[p] = sum_{f=k_lo..k_hi} |sum_t H[p][t] W[t][f]|^2,
  *   W[t][f] = exp(-2 i pi t f / nt) / sqrt(nt), 0-based frequency indices

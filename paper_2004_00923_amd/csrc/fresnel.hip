@@ -17,20 +17,20 @@ namespace hh {
 namespace {
 
 // Rows per workgroup (256 threads where possible).
-template <int N>
+template <int N, int EP = 16>
 constexpr int rows_per_wg() {
-  constexpr int T = FftCfg<N>::T;
+  constexpr int T = FftCfg<N, EP>::T;
   return T >= 256 ? 1 : 256 / T;
 }
 
 // Columns per workgroup: a 128-byte strip (16 complex) where the LDS allows.
-template <int N>
+template <int N, int EP = 16>
 constexpr int cols_per_wg() {
-  constexpr int T = FftCfg<N>::T;
+  constexpr int T = FftCfg<N, EP>::T;
   int w = 1024 / T;
   if (w > 16 && T > 1) w = 256 / T > 16 ? 256 / T : 16;
   if (T == 1) w = 256;
-  while (w > 1 && w * FftCfg<N>::LDSN * 8 > 140000) w >>= 1;
+  while (w > 1 && w * FftCfg<N, EP>::LDSN * 8 > 140000) w >>= 1;
   return w;
 }
 
@@ -47,11 +47,11 @@ struct ColSlot {
 // (the stack's temporal mean), or one float frame.
 enum { kInU16 = 0, kInU16MinusMean = 1, kInF32 = 2 };
 
-template <int N, int ROWS, int IN>
-__global__ __launch_bounds__(ROWS *FftCfg<N>::T) void fresnel_rows(
+template <int N, int EP, int ROWS, int IN>
+__global__ __launch_bounds__(ROWS *(N / fft_e(N, EP))) void fresnel_rows(
     const void *__restrict__ src, const float *__restrict__ mean, int ny, const float2 *__restrict__ chirp_x,
     const float2 *__restrict__ chirp_y, const float2 *__restrict__ tw, float2 *__restrict__ out) {
-  constexpr int E = FftCfg<N>::E, T = FftCfg<N>::T;
+  constexpr int E = FftCfg<N, EP>::E, T = FftCfg<N, EP>::T;
   const int t = threadIdx.x % T;
   const int r = threadIdx.x / T;
   const int row = blockIdx.x * ROWS + r;
@@ -78,11 +78,11 @@ __global__ __launch_bounds__(ROWS *FftCfg<N>::T) void fresnel_rows(
       v[i] = make_float2(val * c.x, val * c.y);
     }
   }
-  if constexpr (FftCfg<N>::P > 1) {
-    __shared__ float2 lds[ROWS * FftCfg<N>::LDSN];
-    fft_passes<N, 16, 0>(v, t, tw, lds + r * FftCfg<N>::LDSN, RowSlot{});
+  if constexpr (FftCfg<N, EP>::P > 1) {
+    __shared__ float2 lds[ROWS * FftCfg<N, EP>::LDSN];
+    fft_passes<N, EP, 0>(v, t, tw, lds + r * FftCfg<N, EP>::LDSN, RowSlot{});
   } else {
-    fft_passes<N, 16, 0>(v, t, tw, (float2 *)nullptr, RowSlot{});
+    fft_passes<N, EP, 0>(v, t, tw, (float2 *)nullptr, RowSlot{});
   }
   if (live) {
 #pragma unroll
@@ -92,11 +92,11 @@ __global__ __launch_bounds__(ROWS *FftCfg<N>::T) void fresnel_rows(
 
 // R16: instead of writing the column FFT back in place, write it scaled by
 // `scale` and rounded to FP16 (round to nearest even) into r16 [frames][N][nx].
-template <int N, int W, bool R16>
-__global__ __launch_bounds__(W *FftCfg<N>::T) void fresnel_cols(float2 *__restrict__ data, int nx,
+template <int N, int EP, int W, bool R16>
+__global__ __launch_bounds__(W *(N / fft_e(N, EP))) void fresnel_cols(float2 *__restrict__ data, int nx,
                                                                const float2 *__restrict__ tw, h2 *__restrict__ r16,
                                                                float scale) {
-  constexpr int E = FftCfg<N>::E, T = FftCfg<N>::T;
+  constexpr int E = FftCfg<N, EP>::E, T = FftCfg<N, EP>::T;
   const int c = threadIdx.x % W;
   const int t = threadIdx.x / W;
   const int col = blockIdx.x * W + c;
@@ -107,11 +107,11 @@ __global__ __launch_bounds__(W *FftCfg<N>::T) void fresnel_cols(float2 *__restri
   float2 v[E];
 #pragma unroll
   for (int i = 0; i < E; ++i) v[i] = live ? base[(size_t)(t + T * i) * nx] : make_float2(0.f, 0.f);
-  if constexpr (FftCfg<N>::P > 1) {
-    __shared__ float2 lds[W * FftCfg<N>::LDSN];
-    fft_passes<N, 16, 0>(v, t, tw, lds, ColSlot<W>{c});
+  if constexpr (FftCfg<N, EP>::P > 1) {
+    __shared__ float2 lds[W * FftCfg<N, EP>::LDSN];
+    fft_passes<N, EP, 0>(v, t, tw, lds, ColSlot<W>{c});
   } else {
-    fft_passes<N, 16, 0>(v, t, tw, (float2 *)nullptr, ColSlot<W>{c});
+    fft_passes<N, EP, 0>(v, t, tw, (float2 *)nullptr, ColSlot<W>{c});
   }
   if (live) {
     if constexpr (R16) {
@@ -149,105 +149,120 @@ __global__ __launch_bounds__(256) void frame_mean(const uint16_t *__restrict__ f
   reinterpret_cast<float4 *>(mean)[q] = make_float4((float)s0 * inv, (float)s1 * inv, (float)s2 * inv, (float)s3 * inv);
 }
 
-template <int N>
-hipError_t rows_n(const Plan &pl, int in_mode, const void *src, const float *mean, int nframes, float2 *out,
-                  hipStream_t s) {
-  constexpr int R = rows_per_wg<N>();
-  dim3 grid((pl.ny + R - 1) / R, nframes), block(R * FftCfg<N>::T);
-  ProfScope ps("fresnel_rows", s);
+// Launch shapes the autotuner chooses between (index = FftShape::rows / ::cols);
+// sizes below kTunedMinN have only shape 0.
+constexpr int kTunedMinN = 512;
+
+template <int N, int EP, int R>
+hipError_t rows_launch(const Plan &pl, int in_mode, const void *src, const float *mean, int nframes, float2 *out,
+                       hipStream_t s) {
+  dim3 grid((pl.ny + R - 1) / R, nframes), block(R * FftCfg<N, EP>::T);
   if (in_mode == kInU16)
-    hipLaunchKernelGGL((fresnel_rows<N, R, kInU16>), grid, block, 0, s, src, mean, pl.ny, pl.chirp_x, pl.chirp_y,
-                       pl.tw_x, out);
+    hipLaunchKernelGGL((fresnel_rows<N, EP, R, kInU16>), grid, block, 0, s, src, mean, pl.ny, pl.chirp_x,
+                       pl.chirp_y, pl.tw_x, out);
   else if (in_mode == kInU16MinusMean)
-    hipLaunchKernelGGL((fresnel_rows<N, R, kInU16MinusMean>), grid, block, 0, s, src, mean, pl.ny, pl.chirp_x,
+    hipLaunchKernelGGL((fresnel_rows<N, EP, R, kInU16MinusMean>), grid, block, 0, s, src, mean, pl.ny, pl.chirp_x,
                        pl.chirp_y, pl.tw_x, out);
   else
-    hipLaunchKernelGGL((fresnel_rows<N, R, kInF32>), grid, block, 0, s, src, mean, pl.ny, pl.chirp_x, pl.chirp_y,
-                       pl.tw_x, out);
+    hipLaunchKernelGGL((fresnel_rows<N, EP, R, kInF32>), grid, block, 0, s, src, mean, pl.ny, pl.chirp_x,
+                       pl.chirp_y, pl.tw_x, out);
   return hipGetLastError();
 }
 
 template <int N>
-hipError_t cols_n(const Plan &pl, int nframes, float2 *data, h2 *r16, float scale, hipStream_t s) {
-  constexpr int W = cols_per_wg<N>();
-  dim3 grid((pl.nx + W - 1) / W, nframes), block(W * FftCfg<N>::T);
-  ProfScope ps(r16 ? "fresnel_cols_r16" : "fresnel_cols", s);
+hipError_t rows_n(const Plan &pl, int shape, int in_mode, const void *src, const float *mean, int nframes,
+                  float2 *out, hipStream_t s) {
+  ProfScope ps("fresnel_rows", s);
+  if constexpr (N >= kTunedMinN) {
+    if (shape == 1) return rows_launch<N, 32, rows_per_wg<N, 32>()>(pl, in_mode, src, mean, nframes, out, s);
+    if (shape == 2) return rows_launch<N, 32, 2>(pl, in_mode, src, mean, nframes, out, s);
+    if (shape == 3) return rows_launch<N, 16, 1>(pl, in_mode, src, mean, nframes, out, s);
+  }
+  return rows_launch<N, 16, rows_per_wg<N, 16>()>(pl, in_mode, src, mean, nframes, out, s);
+}
+
+template <int N, int EP, int W>
+hipError_t cols_launch(const Plan &pl, int nframes, float2 *data, h2 *r16, float scale, hipStream_t s) {
+  dim3 grid((pl.nx + W - 1) / W, nframes), block(W * FftCfg<N, EP>::T);
   if (r16)
-    hipLaunchKernelGGL((fresnel_cols<N, W, true>), grid, block, 0, s, data, pl.nx, pl.tw_y, r16, scale);
+    hipLaunchKernelGGL((fresnel_cols<N, EP, W, true>), grid, block, 0, s, data, pl.nx, pl.tw_y, r16, scale);
   else
-    hipLaunchKernelGGL((fresnel_cols<N, W, false>), grid, block, 0, s, data, pl.nx, pl.tw_y, r16, scale);
+    hipLaunchKernelGGL((fresnel_cols<N, EP, W, false>), grid, block, 0, s, data, pl.nx, pl.tw_y, r16, scale);
   return hipGetLastError();
 }
 
-hipError_t rows_dispatch(const Plan &pl, int in_mode, const void *f, const float *mean, int n, float2 *o,
+template <int N>
+hipError_t cols_n(const Plan &pl, int shape, int nframes, float2 *data, h2 *r16, float scale, hipStream_t s) {
+  ProfScope ps(r16 ? "fresnel_cols_r16" : "fresnel_cols", s);
+  if constexpr (N >= kTunedMinN) {
+    constexpr int Wh = cols_per_wg<N, 16>() / 2 > 0 ? cols_per_wg<N, 16>() / 2 : 1;
+    if (shape == 1) return cols_launch<N, 16, Wh>(pl, nframes, data, r16, scale, s);
+    if (shape == 2) return cols_launch<N, 32, cols_per_wg<N, 32>()>(pl, nframes, data, r16, scale, s);
+  }
+  return cols_launch<N, 16, cols_per_wg<N, 16>()>(pl, nframes, data, r16, scale, s);
+}
+
+hipError_t rows_dispatch(const Plan &pl, int sh, int in_mode, const void *f, const float *mean, int n, float2 *o,
                          hipStream_t s) {
   switch (pl.nx) {
-    case 8: return rows_n<8>(pl, in_mode, f, mean, n, o, s);
-    case 16: return rows_n<16>(pl, in_mode, f, mean, n, o, s);
-    case 32: return rows_n<32>(pl, in_mode, f, mean, n, o, s);
-    case 64: return rows_n<64>(pl, in_mode, f, mean, n, o, s);
-    case 128: return rows_n<128>(pl, in_mode, f, mean, n, o, s);
-    case 256: return rows_n<256>(pl, in_mode, f, mean, n, o, s);
-    case 512: return rows_n<512>(pl, in_mode, f, mean, n, o, s);
-    case 1024: return rows_n<1024>(pl, in_mode, f, mean, n, o, s);
-    case 2048: return rows_n<2048>(pl, in_mode, f, mean, n, o, s);
-    case 4096: return rows_n<4096>(pl, in_mode, f, mean, n, o, s);
+    case 8: return rows_n<8>(pl, sh, in_mode, f, mean, n, o, s);
+    case 16: return rows_n<16>(pl, sh, in_mode, f, mean, n, o, s);
+    case 32: return rows_n<32>(pl, sh, in_mode, f, mean, n, o, s);
+    case 64: return rows_n<64>(pl, sh, in_mode, f, mean, n, o, s);
+    case 128: return rows_n<128>(pl, sh, in_mode, f, mean, n, o, s);
+    case 256: return rows_n<256>(pl, sh, in_mode, f, mean, n, o, s);
+    case 512: return rows_n<512>(pl, sh, in_mode, f, mean, n, o, s);
+    case 1024: return rows_n<1024>(pl, sh, in_mode, f, mean, n, o, s);
+    case 2048: return rows_n<2048>(pl, sh, in_mode, f, mean, n, o, s);
+    case 4096: return rows_n<4096>(pl, sh, in_mode, f, mean, n, o, s);
   }
   return hipErrorInvalidValue;
 }
 
-hipError_t cols_dispatch(const Plan &pl, int n, float2 *d, h2 *r16, float scale, hipStream_t s) {
+hipError_t cols_dispatch(const Plan &pl, int sh, int n, float2 *d, h2 *r16, float scale, hipStream_t s) {
   switch (pl.ny) {
-    case 8: return cols_n<8>(pl, n, d, r16, scale, s);
-    case 16: return cols_n<16>(pl, n, d, r16, scale, s);
-    case 32: return cols_n<32>(pl, n, d, r16, scale, s);
-    case 64: return cols_n<64>(pl, n, d, r16, scale, s);
-    case 128: return cols_n<128>(pl, n, d, r16, scale, s);
-    case 256: return cols_n<256>(pl, n, d, r16, scale, s);
-    case 512: return cols_n<512>(pl, n, d, r16, scale, s);
-    case 1024: return cols_n<1024>(pl, n, d, r16, scale, s);
-    case 2048: return cols_n<2048>(pl, n, d, r16, scale, s);
-    case 4096: return cols_n<4096>(pl, n, d, r16, scale, s);
+    case 8: return cols_n<8>(pl, sh, n, d, r16, scale, s);
+    case 16: return cols_n<16>(pl, sh, n, d, r16, scale, s);
+    case 32: return cols_n<32>(pl, sh, n, d, r16, scale, s);
+    case 64: return cols_n<64>(pl, sh, n, d, r16, scale, s);
+    case 128: return cols_n<128>(pl, sh, n, d, r16, scale, s);
+    case 256: return cols_n<256>(pl, sh, n, d, r16, scale, s);
+    case 512: return cols_n<512>(pl, sh, n, d, r16, scale, s);
+    case 1024: return cols_n<1024>(pl, sh, n, d, r16, scale, s);
+    case 2048: return cols_n<2048>(pl, sh, n, d, r16, scale, s);
+    case 4096: return cols_n<4096>(pl, sh, n, d, r16, scale, s);
   }
   return hipErrorInvalidValue;
-}
-
-// frames per group: about 64 MiB of FP32 holograms, so that a group's
-// row-transformed frames are still in the last-level cache when the column pass
-// reads them back
-int group_frames(const Plan &pl) {
-  const size_t frame_bytes = (size_t)pl.nx * pl.ny * sizeof(float2);
-  const int g = (int)((64u << 20) / frame_bytes);
-  return g < 1 ? 1 : g;
 }
 
 }  // namespace
 
-int fresnel_group_frames(int nx, int ny, int nframes) {
-  const size_t frame_bytes = (size_t)nx * ny * sizeof(float2);
-  int g = (int)((64u << 20) / frame_bytes);
+// Frames are processed in groups so that a group's row-transformed frames are
+// still in the last-level cache when the column pass reads them back: about
+// 64 MiB of FP32 holograms by default, or the tuned count.
+int fresnel_group_frames(int nx, int ny, int nframes, int tuned) {
+  int g = tuned;
+  if (g <= 0) g = (int)((64u << 20) / ((size_t)nx * ny * sizeof(float2)));
   if (g < 1) g = 1;
   return g < nframes ? g : nframes;
 }
 
-hipError_t launch_fresnel(const Plan &pl, const uint16_t *frames, int nframes, float2 *holo,
+hipError_t launch_fresnel(const Plan &pl, const Tune &tu, const uint16_t *frames, int nframes, float2 *holo,
                           hipStream_t s) {
-  const int group = group_frames(pl);
+  const int group = fresnel_group_frames(pl.nx, pl.ny, nframes, tu.group);
   for (int f0 = 0; f0 < nframes; f0 += group) {
     const int n = nframes - f0 < group ? nframes - f0 : group;
     const size_t off = (size_t)f0 * pl.nx * pl.ny;
-    hipError_t e = rows_dispatch(pl, kInU16, frames + off, nullptr, n, holo + off, s);
+    hipError_t e = rows_dispatch(pl, tu.rows, kInU16, frames + off, nullptr, n, holo + off, s);
     if (e != hipSuccess) return e;
-    e = cols_dispatch(pl, n, holo + off, nullptr, 0.f, s);
+    e = cols_dispatch(pl, tu.cols, n, holo + off, nullptr, 0.f, s);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
 }
 
-int fresnel_r16_group(const Plan &pl, int nframes) { return fresnel_group_frames(pl.nx, pl.ny, nframes); }
-
-hipError_t launch_fresnel_r16(const Plan &pl, const uint16_t *frames, int nframes, float *mean, float2 *m,
-                              float2 *group_buf, h2 *r16, float scale, hipStream_t s) {
+hipError_t launch_fresnel_r16(const Plan &pl, const Tune &tu, const uint16_t *frames, int nframes, float *mean,
+                              float2 *m, float2 *group_buf, h2 *r16, float scale, hipStream_t s) {
   const long long npix = (long long)pl.nx * pl.ny;
   {
     ProfScope ps("frame_mean", s);
@@ -255,14 +270,14 @@ hipError_t launch_fresnel_r16(const Plan &pl, const uint16_t *frames, int nframe
                        mean);
   }
   hipError_t e = hipGetLastError();
-  if (e == hipSuccess) e = rows_dispatch(pl, kInF32, mean, nullptr, 1, m, s);
-  if (e == hipSuccess) e = cols_dispatch(pl, 1, m, nullptr, 0.f, s);
-  const int group = fresnel_r16_group(pl, nframes);
+  if (e == hipSuccess) e = rows_dispatch(pl, tu.rows, kInF32, mean, nullptr, 1, m, s);
+  if (e == hipSuccess) e = cols_dispatch(pl, tu.cols, 1, m, nullptr, 0.f, s);
+  const int group = fresnel_group_frames(pl.nx, pl.ny, nframes, tu.group);
   for (int f0 = 0; f0 < nframes && e == hipSuccess; f0 += group) {
     const int n = nframes - f0 < group ? nframes - f0 : group;
     const size_t off = (size_t)f0 * npix;
-    e = rows_dispatch(pl, kInU16MinusMean, frames + off, mean, n, group_buf, s);
-    if (e == hipSuccess) e = cols_dispatch(pl, n, group_buf, r16 + off, scale, s);
+    e = rows_dispatch(pl, tu.rows, kInU16MinusMean, frames + off, mean, n, group_buf, s);
+    if (e == hipSuccess) e = cols_dispatch(pl, tu.cols, n, group_buf, r16 + off, scale, s);
   }
   return e;
 }

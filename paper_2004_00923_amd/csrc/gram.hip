@@ -58,7 +58,7 @@ __device__ __forceinline__ float sum32(float v) {
 // blocks 00, 01, 11 only; Q all four.  TWO = false when n_t <= 16.
 template <bool TWO>
 __global__ __launch_bounds__(256) void gram_partial16(const float2 *__restrict__ H, int nt, long long npix,
-                                                      double *__restrict__ partial) {
+                                                      int pxw, double *__restrict__ partial) {
   constexpr int D = 32;
   constexpr int G4 = 4;  // 16-byte loads per stream per iteration (32 pixels of the wave)
   __shared__ double red[2 * D * D];
@@ -73,12 +73,12 @@ __global__ __launch_bounds__(256) void gram_partial16(const float2 *__restrict__
   double2 a0 = make_double2(0.0, 0.0), a1 = a0;
   double mm = 0.0;
 
-  const long long p0 = ((long long)blockIdx.x * 4 + wave) * kGramPxPerWave;  // first pixel of this wave
+  const long long p0 = ((long long)blockIdx.x * 4 + wave) * pxw;  // first pixel of this wave
   const bool v0 = f < nt, v1 = TWO && (16 + f) < nt;
   const float4 *s0p = reinterpret_cast<const float4 *>(H + (long long)(v0 ? f : 0) * npix + p0) + k;
   const float4 *s1p = reinterpret_cast<const float4 *>(H + (long long)(v1 ? 16 + f : 0) * npix + p0) + k;
 
-  for (int q0 = 0; q0 < kGramPxPerWave; q0 += 8 * G4) {
+  for (int q0 = 0; q0 < pxw; q0 += 8 * G4) {
     float4 h0[G4], h1[G4];
 #pragma unroll
     for (int g = 0; g < G4; ++g) {
@@ -176,9 +176,9 @@ __global__ __launch_bounds__(256) void gram_partial16(const float2 *__restrict__
 // 32 < n_t <= 64 path on v_mfma_f32_32x32x2f32: lane (fr, half) holds frames fr and
 // 32 + fr; the two half-waves take one half of the wave's pixels each.
 __global__ __launch_bounds__(256) void gram_partial64(const float2 *__restrict__ H, int nt, long long npix,
-                                                      double *__restrict__ partial) {
+                                                      int pxw, double *__restrict__ partial) {
   constexpr int D = 64;
-  constexpr int HALF = kGramPxPerWave / 2;  // pixels per half-wave
+  const int HALF = pxw / 2;  // pixels per half-wave
   constexpr int G4 = 4;
   __shared__ double red[2 * D * D];
   __shared__ double2 ared[4][2][D];
@@ -200,7 +200,7 @@ __global__ __launch_bounds__(256) void gram_partial64(const float2 *__restrict__
   double2 a_acc[2] = {make_double2(0.0, 0.0), make_double2(0.0, 0.0)};
   double mm_acc = 0.0;
 
-  const long long p0 = ((long long)blockIdx.x * 4 + wave) * kGramPxPerWave + (long long)half * HALF;
+  const long long p0 = ((long long)blockIdx.x * 4 + wave) * pxw + (long long)half * HALF;
   const float4 *src[2];
   bool valid[2];
 #pragma unroll
@@ -392,7 +392,7 @@ __device__ __forceinline__ float pow2_scale(float mx, float lim) {
 
 template <int FMT, bool SPLIT>
 __global__ __launch_bounds__(256) void gram_partial_lp(const float2 *__restrict__ H, int nt, long long npix,
-                                                       double *__restrict__ partial) {
+                                                       int pxw, double *__restrict__ partial) {
   constexpr int D = 32;
   typedef LpOp<FMT> Op;
   typedef typename Op::U U;
@@ -404,7 +404,7 @@ __global__ __launch_bounds__(256) void gram_partial_lp(const float2 *__restrict_
   const int lane = tid & 63, wave = tid >> 6;
   const int f = lane & 15, kq = lane >> 4;
   const float inv_nt = 1.0f / (float)nt;
-  const long long p0 = ((long long)blockIdx.x * 4 + wave) * kGramPxPerWave;
+  const long long p0 = ((long long)blockIdx.x * 4 + wave) * pxw;
   const bool v0 = f < nt, v1 = (16 + f) < nt;
   const float4 *s0p = reinterpret_cast<const float4 *>(H + (long long)(v0 ? f : 0) * npix + p0) + kq;
   const float4 *s1p = reinterpret_cast<const float4 *>(H + (long long)(v1 ? 16 + f : 0) * npix + p0) + kq;
@@ -421,7 +421,7 @@ __global__ __launch_bounds__(256) void gram_partial_lp(const float2 *__restrict_
       x1[2 * g + 1] = make_float2(b.z, b.w);
     }
   };
-  constexpr int STEPS = kGramPxPerWave / 32;
+  const int STEPS = pxw / 32;
 
   // pass A (FP16, FP8): largest |Re|, |Im| of R, per wave or per wave and frame
   float sc0 = 1.f, sc1 = 1.f;
@@ -562,7 +562,7 @@ __global__ __launch_bounds__(256) void gram_partial_lp(const float2 *__restrict_
 // FP32 over 8 pixels, then FP64.  Lane (f, kq) holds frames f and 16 + f of the 8
 // pixels 8 kq .. 8 kq + 7 of each 32-pixel step (two 16-byte loads per frame).
 __global__ __launch_bounds__(256) void gram_partial_r16(const h2 *__restrict__ R, const float2 *__restrict__ M,
-                                                         int nt, long long npix, float inv_s,
+                                                         int nt, long long npix, int pxw, float inv_s,
                                                          double *__restrict__ partial) {
   constexpr int D = 32;
   __shared__ double red[2 * D * D];
@@ -571,7 +571,7 @@ __global__ __launch_bounds__(256) void gram_partial_r16(const h2 *__restrict__ R
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int f = lane & 15, kq = lane >> 4;
-  const long long p0 = ((long long)blockIdx.x * 4 + wave) * kGramPxPerWave;
+  const long long p0 = ((long long)blockIdx.x * 4 + wave) * pxw;
   const bool v0 = f < nt, v1 = (16 + f) < nt;
   const uint4 *r0p = reinterpret_cast<const uint4 *>(R + (long long)(v0 ? f : 0) * npix + p0) + 2 * kq;
   const uint4 *r1p = reinterpret_cast<const uint4 *>(R + (long long)(v1 ? 16 + f : 0) * npix + p0) + 2 * kq;
@@ -584,7 +584,7 @@ __global__ __launch_bounds__(256) void gram_partial_r16(const h2 *__restrict__ R
   v4f S00 = {0.f, 0.f, 0.f, 0.f}, S01 = S00, S11 = S00, Q00 = S00, Q01 = S00, Q10 = S00, Q11 = S00;
   double2 a0 = make_double2(0.0, 0.0), a1 = a0;
   double mm = 0.0;
-  constexpr int STEPS = kGramPxPerWave / 32;
+  const int STEPS = pxw / 32;
   for (int j = 0; j < STEPS; ++j) {
     const bool in = p0 + 32 * j + 8 * kq < npix;  // npix is a multiple of 8
     U8 x0, x1;
@@ -714,11 +714,12 @@ __global__ __launch_bounds__(256) void gram_finalize(const double *__restrict__ 
 
 }  // namespace
 
-GramLayout gram_layout(int nt, long long npix) {
+GramLayout gram_layout(int nt, long long npix, int pxw) {
   GramLayout L;
   L.nb = nt <= 32 ? 1 : 2;
   L.D = 32 * L.nb;
-  L.chunks = (npix + kGramPxPerWave - 1) / kGramPxPerWave;  // one chunk per wave
+  L.pxw = pxw;
+  L.chunks = (npix + pxw - 1) / pxw;  // one chunk per wave
   L.groups = (int)((L.chunks + 3) / 4);
   L.groups2 = L.groups < 16 ? L.groups : 16;
   L.partial_bytes = (size_t)L.groups * partial_len(L.D) * sizeof(double);
@@ -736,20 +737,20 @@ hipError_t launch_gram(const GramLayout &L, const float2 *holo, int nt, long lon
     ProfScope ps("gram_partial_lp", s);
     const dim3 g(L.groups), b(256);
     switch (precision) {
-      case HH_BF16: hipLaunchKernelGGL((gram_partial_lp<kLpBF16, false>), g, b, 0, s, holo, nt, npix, partial); break;
-      case HH_BF16X3: hipLaunchKernelGGL((gram_partial_lp<kLpBF16, true>), g, b, 0, s, holo, nt, npix, partial); break;
-      case HH_FP16: hipLaunchKernelGGL((gram_partial_lp<kLpFP16, false>), g, b, 0, s, holo, nt, npix, partial); break;
-      case HH_FP16X3: hipLaunchKernelGGL((gram_partial_lp<kLpFP16, true>), g, b, 0, s, holo, nt, npix, partial); break;
-      default: hipLaunchKernelGGL((gram_partial_lp<kLpFP8, false>), g, b, 0, s, holo, nt, npix, partial); break;
+      case HH_BF16: hipLaunchKernelGGL((gram_partial_lp<kLpBF16, false>), g, b, 0, s, holo, nt, npix, L.pxw, partial); break;
+      case HH_BF16X3: hipLaunchKernelGGL((gram_partial_lp<kLpBF16, true>), g, b, 0, s, holo, nt, npix, L.pxw, partial); break;
+      case HH_FP16: hipLaunchKernelGGL((gram_partial_lp<kLpFP16, false>), g, b, 0, s, holo, nt, npix, L.pxw, partial); break;
+      case HH_FP16X3: hipLaunchKernelGGL((gram_partial_lp<kLpFP16, true>), g, b, 0, s, holo, nt, npix, L.pxw, partial); break;
+      default: hipLaunchKernelGGL((gram_partial_lp<kLpFP8, false>), g, b, 0, s, holo, nt, npix, L.pxw, partial); break;
     }
   } else {
     ProfScope ps("gram_partial", s);
     if (nt <= 16)
-      hipLaunchKernelGGL(gram_partial16<false>, dim3(L.groups), dim3(256), 0, s, holo, nt, npix, partial);
+      hipLaunchKernelGGL(gram_partial16<false>, dim3(L.groups), dim3(256), 0, s, holo, nt, npix, L.pxw, partial);
     else if (nt <= 32)
-      hipLaunchKernelGGL(gram_partial16<true>, dim3(L.groups), dim3(256), 0, s, holo, nt, npix, partial);
+      hipLaunchKernelGGL(gram_partial16<true>, dim3(L.groups), dim3(256), 0, s, holo, nt, npix, L.pxw, partial);
     else
-      hipLaunchKernelGGL(gram_partial64, dim3(L.groups), dim3(256), 0, s, holo, nt, npix, partial);
+      hipLaunchKernelGGL(gram_partial64, dim3(L.groups), dim3(256), 0, s, holo, nt, npix, L.pxw, partial);
   }
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
@@ -760,7 +761,7 @@ hipError_t launch_gram_r16(const GramLayout &L, const h2 *r16, const float2 *m, 
                            double *partial, double *partial2, double *cov, hipStream_t s) {
   {
     ProfScope ps("gram_partial_r16", s);
-    hipLaunchKernelGGL(gram_partial_r16, dim3(L.groups), dim3(256), 0, s, r16, m, nt, npix, inv_s, partial);
+    hipLaunchKernelGGL(gram_partial_r16, dim3(L.groups), dim3(256), 0, s, r16, m, nt, npix, L.pxw, inv_s, partial);
   }
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;

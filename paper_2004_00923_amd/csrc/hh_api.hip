@@ -1,6 +1,7 @@
 // C ABI of libhh: host-side validation, device-table cache, workspace layout and
 // the ordered launch of the hot-path kernels.  No entry point waits for the
 // device except the first-call table build of a configuration.
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -225,6 +226,52 @@ hh_status check_precision(const hh_params *p, bool from_frames) {
 
 bool aligned(const void *ptr, size_t a) { return ((uintptr_t)ptr % a) == 0; }
 
+// ------------------------------------------------------------ tuning ----
+// Launch choices per problem shape, filled by hh_autotune or hh_tuning_set:
+// FFT shapes and the group size per (device, nx, ny); the covariance split-K
+// chunk per (device, nx*ny, nt, precision).  Absent entries use the defaults.
+using FftKey = std::tuple<int, int, int>;
+using GramKey = std::tuple<int, long long, int, int>;
+std::mutex g_tune_mu;
+std::map<FftKey, Tune> g_fft_tune;
+std::map<GramKey, int> g_gram_tune;
+
+int current_device() {
+  int d = 0;
+  return hipGetDevice(&d) == hipSuccess ? d : -1;
+}
+
+Tune get_tune(const hh_params &p) {
+  const int d = current_device();
+  std::lock_guard<std::mutex> g(g_tune_mu);
+  Tune t;
+  auto f = g_fft_tune.find(FftKey{d, p.nx, p.ny});
+  if (f != g_fft_tune.end()) t = f->second;
+  auto q = g_gram_tune.find(GramKey{d, (long long)p.nx * p.ny, p.nt, p.precision});
+  t.pxw = q != g_gram_tune.end() ? q->second : kGramPxwMin;
+  return t;
+}
+
+void put_tune(const hh_params &p, const Tune &t) {
+  const int d = current_device();
+  std::lock_guard<std::mutex> g(g_tune_mu);
+  g_fft_tune[FftKey{d, p.nx, p.ny}] = t;
+  g_gram_tune[GramKey{d, (long long)p.nx * p.ny, p.nt, p.precision}] = t.pxw;
+}
+
+int default_group(const hh_params &p) { return fresnel_group_frames(p.nx, p.ny, 1 << 30, 0); }
+
+hh_status check_tune(const hh_params &p, const hh_tuning &t) {
+  const int nrows = p.nx >= 512 ? 4 : 1, ncols = p.ny >= 512 ? 3 : 1;
+  if (t.fft_rows < 0 || t.fft_rows >= nrows) return fail(HH_E_INVALID, "fft_rows=%d: %d shape(s) at nx=%d", t.fft_rows, nrows, p.nx);
+  if (t.fft_cols < 0 || t.fft_cols >= ncols) return fail(HH_E_INVALID, "fft_cols=%d: %d shape(s) at ny=%d", t.fft_cols, ncols, p.ny);
+  if (t.gram_pxw != 256 && t.gram_pxw != 512 && t.gram_pxw != 1024)
+    return fail(HH_E_INVALID, "gram_pxw=%d: must be 256, 512 or 1024", t.gram_pxw);
+  if (t.group < 0 || t.group > default_group(p))
+    return fail(HH_E_INVALID, "group=%d: must be in [0, %d] (0 = default)", t.group, default_group(p));
+  return HH_OK;
+}
+
 struct PipeLayout {
   GramLayout g;
   bool r16 = false;  // FP16 storage form
@@ -241,7 +288,7 @@ PipeLayout pipe_layout(const hh_params *p, bool with_holo = true) {
   size_t o = 0;
   if (L.r16) {
     L.r16buf = o; o = align_up(o + (size_t)p->nt * npix * sizeof(h2));
-    L.group = o; o = align_up(o + (size_t)fresnel_group_frames(p->nx, p->ny, p->nt) * npix * sizeof(float2));
+    L.group = o; o = align_up(o + (size_t)fresnel_group_frames(p->nx, p->ny, p->nt, 0) * npix * sizeof(float2));
     L.mean = o; o = align_up(o + (size_t)npix * sizeof(float));
     L.m = o; o = align_up(o + (size_t)npix * sizeof(float2));
   } else {
@@ -279,6 +326,8 @@ struct StackViews {
 hipError_t enqueue_front(const hh_params &p, const Plan *pl, const PipeLayout &L, char *ws, const uint16_t *frames,
                          const float2 *holo, StackViews &v, hipStream_t s) {
   const long long npix = (long long)p.nx * p.ny;
+  const Tune tu = get_tune(p);
+  const GramLayout gl = gram_layout(p.nt, npix, tu.pxw);  // offsets in L are sized for the smallest chunk
   double *part = reinterpret_cast<double *>(ws + L.part), *part2 = reinterpret_cast<double *>(ws + L.part2);
   v.cov = reinterpret_cast<double *>(ws + L.cov);
   if (L.r16) {
@@ -287,20 +336,20 @@ hipError_t enqueue_front(const hh_params &p, const Plan *pl, const PipeLayout &L
     v.inv_s = r16_inv_scale(npix);
     v.r16 = r;
     v.m = m;
-    hipError_t e = launch_fresnel_r16(*pl, frames, p.nt, reinterpret_cast<float *>(ws + L.mean), m,
+    hipError_t e = launch_fresnel_r16(*pl, tu, frames, p.nt, reinterpret_cast<float *>(ws + L.mean), m,
                                       reinterpret_cast<float2 *>(ws + L.group), r, 1.0f / v.inv_s, s);
     if (e != hipSuccess) return e;
-    return launch_gram_r16(L.g, r, m, p.nt, npix, v.inv_s, part, part2, v.cov, s);
+    return launch_gram_r16(gl, r, m, p.nt, npix, v.inv_s, part, part2, v.cov, s);
   }
   if (frames) {
     float2 *H = reinterpret_cast<float2 *>(ws + L.holo);
-    hipError_t e = launch_fresnel(*pl, frames, p.nt, H, s);
+    hipError_t e = launch_fresnel(*pl, tu, frames, p.nt, H, s);
     if (e != hipSuccess) return e;
     v.H = H;
   } else {
     v.H = holo;
   }
-  return launch_gram(L.g, v.H, p.nt, npix, part, part2, v.cov, s, p.precision);
+  return launch_gram(gl, v.H, p.nt, npix, part, part2, v.cov, s, p.precision);
 }
 
 hipError_t enqueue_back(const hh_params &p, const StackViews &v, const double *V, float *image, hipStream_t s) {
@@ -421,7 +470,8 @@ hh_status hh_fresnel(const hh_params *p, const uint16_t *frames, int32_t nframes
   if (!aligned(frames, 2) || !aligned(holo, 16)) return fail(HH_E_INVALID, "frames/holo misaligned");
   const Plan *pl = get_plan(*p);
   if (!pl) return HH_E_DEVICE;
-  hipError_t e = launch_fresnel(*pl, frames, nframes, reinterpret_cast<float2 *>(holo), (hipStream_t)stream);
+  hipError_t e =
+      launch_fresnel(*pl, get_tune(*p), frames, nframes, reinterpret_cast<float2 *>(holo), (hipStream_t)stream);
   if (e != hipSuccess) return device_fail(e, "hh_fresnel");
   return HH_OK;
 }
@@ -436,9 +486,10 @@ hh_status hh_covariance(const hh_params *p, const float *holo, double *cov, void
   if (!workspace || ws_bytes < need || !aligned(workspace, 256))
     return fail(HH_E_WORKSPACE, "covariance workspace: need %zu bytes (256-byte aligned), got %zu", need, ws_bytes);
   const long long npix = (long long)p->nx * p->ny;
-  const GramLayout g = gram_layout(p->nt, npix);
+  const GramLayout g = gram_layout(p->nt, npix);                     // sizes the workspace
+  const GramLayout gl = gram_layout(p->nt, npix, get_tune(*p).pxw);  // the launch
   char *ws = static_cast<char *>(workspace);
-  hipError_t e = launch_gram(g, reinterpret_cast<const float2 *>(holo), p->nt, npix, reinterpret_cast<double *>(ws),
+  hipError_t e = launch_gram(gl, reinterpret_cast<const float2 *>(holo), p->nt, npix, reinterpret_cast<double *>(ws),
                              reinterpret_cast<double *>(ws + align_up(g.partial_bytes)), cov, (hipStream_t)stream,
                              p->precision);
   if (e != hipSuccess) return device_fail(e, "hh_covariance");
@@ -632,6 +683,101 @@ void hh_graph_destroy(hh_graph *g) {
   if (g->exec) (void)hipGraphExecDestroy(g->exec);
   if (g->graph) (void)hipGraphDestroy(g->graph);
   delete g;
+}
+
+hh_status hh_tuning_get(const hh_params *p, hh_tuning *t) {
+  if (!p || !t) return fail(HH_E_INVALID, "params and tuning must be non-NULL");
+  hh_status st;
+  if ((st = check_shape(p))) return st;
+  const Tune tu = get_tune(*p);
+  *t = hh_tuning{tu.rows, tu.cols, tu.pxw, tu.group};
+  return HH_OK;
+}
+
+hh_status hh_tuning_set(const hh_params *p, const hh_tuning *t) {
+  if (!p || !t) return fail(HH_E_INVALID, "params and tuning must be non-NULL");
+  hh_status st;
+  if ((st = check_shape(p)) || (st = check_tune(*p, *t))) return st;
+  put_tune(*p, Tune{t->fft_rows, t->fft_cols, t->gram_pxw, t->group});
+  return HH_OK;
+}
+
+void hh_tuning_reset(void) {
+  std::lock_guard<std::mutex> g(g_tune_mu);
+  g_fft_tune.clear();
+  g_gram_tune.clear();
+}
+
+hh_status hh_autotune(const hh_params *p, const uint16_t *frames, void *workspace, size_t ws_bytes, int32_t reps,
+                      hh_tuning *best, void *stream) {
+  if (!p || !frames) return fail(HH_E_INVALID, "params and frames must be non-NULL");
+  if (reps < 1 || reps > 1000) return fail(HH_E_INVALID, "reps=%d must be in [1, 1000]", reps);
+  hh_status st;
+  if ((st = check_optics(p)) || (st = check_stack(p)) || (st = check_select(p)) || (st = check_precision(p, true)))
+    return st;
+  hipStream_t s = (hipStream_t)stream;
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone)
+    return fail(HH_E_INVALID, "hh_autotune times real launches: not under stream capture");
+  const long long npix = (long long)p->nx * p->ny;
+  hipError_t e = hipSuccess;
+  float *img = nullptr;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  e = hipMalloc(&img, (size_t)npix * sizeof(float));
+  if (e == hipSuccess) e = hipEventCreate(&ev0);
+  if (e == hipSuccess) e = hipEventCreate(&ev1);
+  // median time of `reps` pipelines under tuning t (one untimed run first)
+  auto time_of = [&](const Tune &t, float &ms) -> hh_status {
+    put_tune(*p, t);
+    std::vector<float> v;
+    for (int r = 0; r <= reps; ++r) {
+      if (hipEventRecord(ev0, s) != hipSuccess) return device_fail(hipGetLastError(), "hh_autotune");
+      const hh_status q = hh_pipeline(p, frames, img, nullptr, nullptr, nullptr, workspace, ws_bytes, stream);
+      if (q != HH_OK) return q;
+      hipError_t ee = hipEventRecord(ev1, s);
+      if (ee == hipSuccess) ee = hipEventSynchronize(ev1);
+      float x = 0.f;
+      if (ee == hipSuccess) ee = hipEventElapsedTime(&x, ev0, ev1);
+      if (ee != hipSuccess) return device_fail(ee, "hh_autotune");
+      if (r > 0) v.push_back(x);
+    }
+    std::sort(v.begin(), v.end());
+    ms = v[v.size() / 2];
+    return HH_OK;
+  };
+  const Tune saved = get_tune(*p);
+  Tune cur = saved;
+  cur.rows = cur.cols = 0;
+  st = e == hipSuccess ? HH_OK : device_fail(e, "hh_autotune (setup)");
+  float best_ms = 0.f;
+  if (st == HH_OK) st = time_of(cur, best_ms);
+  // coordinate descent: row shape, column shape, group size, split-K chunk
+  const int dg = default_group(*p);
+  std::vector<std::pair<int Tune::*, std::vector<int>>> axes = {
+      {&Tune::rows, p->nx >= 512 ? std::vector<int>{0, 1, 2, 3} : std::vector<int>{0}},
+      {&Tune::cols, p->ny >= 512 ? std::vector<int>{0, 1, 2} : std::vector<int>{0}},
+      {&Tune::group, {0, std::max(1, dg / 2), std::max(1, dg / 4)}},
+      {&Tune::pxw, {256, 512, 1024}}};
+  for (auto &ax : axes) {
+    for (int val : ax.second) {
+      if (st != HH_OK) break;
+      if (cur.*(ax.first) == val) continue;
+      Tune t = cur;
+      t.*(ax.first) = val;
+      float ms = 0.f;
+      st = time_of(t, ms);
+      if (st == HH_OK && ms < best_ms) {
+        best_ms = ms;
+        cur = t;
+      }
+    }
+  }
+  put_tune(*p, st == HH_OK ? cur : saved);
+  if (img) (void)hipFree(img);
+  if (ev0) (void)hipEventDestroy(ev0);
+  if (ev1) (void)hipEventDestroy(ev1);
+  if (st == HH_OK && best) *best = hh_tuning{cur.rows, cur.cols, cur.pxw, cur.group};
+  return st;
 }
 
 void hh_plan_cache_clear(void) {

@@ -39,29 +39,37 @@ struct ProfScope {
 
 // ---- launchers (each returns hipSuccess or the launch error) ----
 
+struct Tune;
 // Step (a): row pass (uint16 -> chirp -> row FFT) then in-place column FFT.
-hipError_t launch_fresnel(const Plan &pl, const uint16_t *frames, int nframes, float2 *holo,
+hipError_t launch_fresnel(const Plan &pl, const Tune &tu, const uint16_t *frames, int nframes, float2 *holo,
                           hipStream_t s);
 // FP16 storage form of step (a): mean[p] = temporal mean of the frames (float),
 // m = Fresnel(mean) (complex64), r16[t] = FP16(scale * Fresnel(frame_t - mean)).
-// group_buf holds fresnel_r16_group(pl, nframes) FP32 frames.
+// group_buf holds fresnel_group_frames(nx, ny, nframes, tu.group) FP32 frames.
 typedef _Float16 h2 __attribute__((ext_vector_type(2)));
-int fresnel_r16_group(const Plan &pl, int nframes);
-int fresnel_group_frames(int nx, int ny, int nframes);
-hipError_t launch_fresnel_r16(const Plan &pl, const uint16_t *frames, int nframes, float *mean, float2 *m,
-                              float2 *group_buf, h2 *r16, float scale, hipStream_t s);
+int fresnel_group_frames(int nx, int ny, int nframes, int tuned);
+hipError_t launch_fresnel_r16(const Plan &pl, const Tune &tu, const uint16_t *frames, int nframes, float *mean,
+                              float2 *m, float2 *group_buf, h2 *r16, float scale, hipStream_t s);
 
 // Step (b): split-K Gram partials, fixed-order reduction, Hermitian assembly.
 struct GramLayout {
   int nb = 1;              // 32-frame blocks (1 or 2)
   int D = 32;              // 32 * nb
-  long long chunks = 0;    // pixel chunks of kGramPxPerWave pixels (one per wave)
+  int pxw = 256;           // pixels per wave (split-K chunk); FP32 sums of <= 2 pxw products
+  long long chunks = 0;    // pixel chunks of pxw pixels (one per wave)
   int groups = 0;          // workgroups of the partial kernel
   int groups2 = 0;         // second-level partial count
   size_t partial_bytes = 0, partial2_bytes = 0;
 };
-constexpr int kGramPxPerWave = 256;  // pixels per wave (FP32 sums <= 256 px per accumulator)
-GramLayout gram_layout(int nt, long long npix);
+// Tuned launch choices for one problem shape (see the autotuner in hh_api.hip).
+struct Tune {
+  int rows = 0;      // row-FFT launch shape (0..3)
+  int cols = 0;      // column-FFT launch shape (0..2)
+  int pxw = 256;     // Gram pixels per wave: 256, 512 or 1024
+  int group = 0;     // frames per Fresnel group, 0 = about 64 MiB of holograms
+};
+constexpr int kGramPxwMin = 256;  // the workspace is sized for the smallest split-K chunk
+GramLayout gram_layout(int nt, long long npix, int pxw = kGramPxwMin);
 // precision: HH_FP32, or a low-precision form of the R^H R contraction (n_t <= 32;
 // larger stacks use the FP32 form).
 hipError_t launch_gram(const GramLayout &L, const float2 *holo, int nt, long long npix,

@@ -68,6 +68,14 @@ class hh_window(ctypes.Structure):
                 ("evecs", ctypes.c_void_p), ("info", ctypes.c_void_p)]
 
 
+class hh_tuning(ctypes.Structure):
+    _fields_ = [("fft_rows", ctypes.c_int32), ("fft_cols", ctypes.c_int32), ("gram_pxw", ctypes.c_int32),
+                ("group", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {f: int(getattr(self, f)) for f, _ in self._fields_}
+
+
 class HHError(RuntimeError):
     def __init__(self, status: int, detail: str):
         super().__init__(f"hh status {status}: {detail}")
@@ -99,6 +107,11 @@ SIGNATURES = {
                                          ctypes.c_size_t, ctypes.POINTER(ctypes.c_void_p)]),
     "hh_graph_launch": (ctypes.c_int32, [_P, _P]),
     "hh_graph_destroy": (None, [_P]),
+    "hh_tuning_get": (ctypes.c_int32, [ctypes.POINTER(hh_params), ctypes.POINTER(hh_tuning)]),
+    "hh_tuning_set": (ctypes.c_int32, [ctypes.POINTER(hh_params), ctypes.POINTER(hh_tuning)]),
+    "hh_tuning_reset": (None, []),
+    "hh_autotune": (ctypes.c_int32, [ctypes.POINTER(hh_params), _P, _P, ctypes.c_size_t, ctypes.c_int32,
+                                     ctypes.POINTER(hh_tuning), _P]),
     "hh_status_string": (ctypes.c_char_p, [ctypes.c_int32]),
     "hh_last_error": (ctypes.c_char_p, []),
     "hh_plan_cache_clear": (None, []),
@@ -342,6 +355,31 @@ def hh_analyze_batch(ps, holos, images, workspace, evals=None, evecs=None, infos
     _check(lib().hh_analyze_batch(_param_array(ps), n, wins, _ptr(workspace),
                                   workspace.numel() * workspace.element_size(), _stream(stream)))
     return images
+
+
+def tuning_get(p: Params) -> dict:
+    t = hh_tuning()
+    _check(lib().hh_tuning_get(ctypes.byref(p.c()), ctypes.byref(t)))
+    return t.as_dict()
+
+
+def tuning_set(p: Params, fft_rows=0, fft_cols=0, gram_pxw=256, group=0):
+    t = hh_tuning(fft_rows, fft_cols, gram_pxw, group)
+    _check(lib().hh_tuning_set(ctypes.byref(p.c()), ctypes.byref(t)))
+
+
+def tuning_reset():
+    lib().hh_tuning_reset()
+
+
+def autotune(p: Params, frames, workspace, reps: int = 5, stream=None) -> dict:
+    """Times the launch choices on `frames` and keeps the fastest for this shape; see include/hh.h."""
+    import torch
+    _dev_tensor(frames, torch.uint16, (p.nt, p.ny, p.nx), "frames")
+    t = hh_tuning()
+    _check(lib().hh_autotune(ctypes.byref(p.c()), _ptr(frames), _ptr(workspace),
+                             workspace.numel() * workspace.element_size(), reps, ctypes.byref(t), _stream(stream)))
+    return t.as_dict()
 
 
 def alloc_workspace(nbytes: int, device="cuda"):

@@ -143,3 +143,29 @@ def test_status_strings():
     for s in range(6):
         assert L.hh_status_string(s).decode()
     assert L.hh_status_string(77).decode() == "unknown status"
+
+
+def test_tuning_validation_and_roundtrip():
+    hh.tuning_reset()
+    p = hh.Params(nx=1024, ny=1024, nt=32, k_lo=2, k_hi=31)
+    assert hh.tuning_get(p) == {"fft_rows": 0, "fft_cols": 0, "gram_pxw": 256, "group": 0}
+    hh.tuning_set(p, fft_rows=1, fft_cols=2, gram_pxw=1024, group=4)
+    assert hh.tuning_get(p) == {"fft_rows": 1, "fft_cols": 2, "gram_pxw": 1024, "group": 4}
+    # FFT choices follow (nx, ny); the split-K chunk follows (nx * ny, nt, precision)
+    q = hh.Params(nx=1024, ny=1024, nt=16, k_lo=2, k_hi=15)
+    assert hh.tuning_get(q)["fft_rows"] == 1 and hh.tuning_get(q)["gram_pxw"] == 256
+    for bad in ({"fft_rows": 4}, {"fft_cols": 3}, {"gram_pxw": 300}, {"group": -1}, {"group": 9}):
+        with pytest.raises(hh.HHError) as ei:
+            hh.tuning_set(p, **bad)
+        assert ei.value.status == hh.HH_E_INVALID
+    small = hh.Params(nx=128, ny=128, nt=32, k_lo=2, k_hi=31)
+    with pytest.raises(hh.HHError):
+        hh.tuning_set(small, fft_rows=1)        # one row shape below 512 points
+    hh.tuning_reset()
+    assert hh.tuning_get(p)["fft_rows"] == 0
+    # the autotuner validates before any device work
+    L = hh.lib()
+    t = hh.hh_tuning()
+    assert L.hh_autotune(ctypes.byref(p.c()), None, None, 0, 3, ctypes.byref(t), None) == hh.HH_E_INVALID
+    assert L.hh_autotune(ctypes.byref(p.c()), ctypes.c_void_p(16), None, 0, 0, ctypes.byref(t), None) == \
+        hh.HH_E_INVALID

@@ -1,0 +1,68 @@
+"""GPU: every launch choice the autotuner can pick gives a result within the FP32
+bar of the oracle, and the autotuner itself runs, keeps a valid choice, and the
+pipeline under it still matches the oracle."""
+import numpy as np
+import pytest
+
+import oracle
+from gpu_util import LAM, PITCH, Z, rel, say, to_dev, to_np
+from paper_2004_00923_amd.synth import gen_stack
+
+pytestmark = pytest.mark.gpu
+
+IMG_TOL = 1e-5
+
+
+@pytest.fixture(scope="module")
+def hh():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    import paper_2004_00923_amd.hh as hh_mod
+    hh_mod.lib()
+    hh_mod.tuning_reset()
+    yield hh_mod
+    hh_mod.tuning_reset()
+
+
+def _run(hh, p, frames):
+    import torch
+    ws = hh.alloc_workspace(hh.workspace_bytes(p))
+    img = torch.empty((p.ny, p.nx), dtype=torch.float32, device="cuda")
+    hh.hh_pipeline(p, frames, img, ws)
+    return to_np(img)
+
+
+@pytest.fixture(scope="module")
+def case(hh):
+    # 512 x 1024 frames: both FFT lengths have every launch shape
+    nt, ny, nx = 32, 512, 1024
+    f = gen_stack(77, nt, ny, nx)
+    r = oracle.pipeline_ref(f, LAM, Z, PITCH, 2, nt - 1)
+    return f, to_dev(f), r["image"]
+
+
+@pytest.mark.parametrize("rows,cols,pxw,group", [(0, 0, 256, 0), (1, 0, 256, 0), (2, 0, 256, 0), (3, 0, 256, 0),
+                                                 (0, 1, 256, 0), (0, 2, 256, 0), (0, 0, 512, 0), (0, 0, 1024, 0),
+                                                 (0, 0, 256, 3), (2, 2, 1024, 1)])
+@pytest.mark.parametrize("precision", ["fp32", "fp16store"])
+def test_every_launch_choice_meets_the_bar(hh, case, rows, cols, pxw, group, precision):
+    f, fd, ref = case
+    p = hh.Params(nx=1024, ny=512, nt=32, k_lo=2, k_hi=31, precision=hh.PRECISIONS[precision])
+    hh.tuning_set(p, fft_rows=rows, fft_cols=cols, gram_pxw=pxw, group=group)
+    try:
+        e = rel(_run(hh, p, fd), ref)
+    finally:
+        hh.tuning_reset()
+    say(f"tuning rows={rows} cols={cols} pxw={pxw} group={group} {precision}: image {e:.2e}")
+    assert e <= (IMG_TOL if precision == "fp32" else 1e-3)
+
+
+def test_autotune_picks_a_valid_choice(hh, case):
+    f, fd, ref = case
+    p = hh.Params(nx=1024, ny=512, nt=32, k_lo=2, k_hi=31)
+    ws = hh.alloc_workspace(hh.workspace_bytes(p))
+    best = hh.autotune(p, fd, ws, reps=3)
+    say(f"autotune 32x512x1024: {best}")
+    assert hh.tuning_get(p) == best
+    assert rel(_run(hh, p, fd), ref) <= IMG_TOL
+    hh.tuning_reset()
