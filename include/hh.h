@@ -65,8 +65,12 @@ enum {
  * covariance runs on FP16 MFMA straight from R, and the projection of step (d)
  * reads m + R / s.  It halves the hologram traffic and applies only to the
  * entry points that start from frames (hh_pipeline, hh_pipeline_batch,
- * hh_graph_create).  Forms other than HH_FP32 require nt <= 32 (else
- * HH_E_UNSUPPORTED).  The projection is FP32/FP64 in every form. */
+ * hh_graph_create).  HH_EXACT computes C without the holograms: the input chirp
+ * has unit modulus and the unnormalised DFT satisfies F^H F = nx ny I, so C of
+ * Eq. (4) equals nx ny I^T I for the real interferogram matrix I, an integer Gram
+ * evaluated exactly in FP64 (same entry points as HH_FP16_STORE).  Forms 1-6
+ * require nt <= 32 (else HH_E_UNSUPPORTED).  The projection is FP32/FP64 in
+ * every form. */
 enum {
   HH_FP32 = 0,      /* FP32 operands, FP32 sums of <= 512 products, FP64 reduction */
   HH_BF16 = 1,      /* BF16 operands (round to nearest even) on MFMA, FP32 accumulation */
@@ -74,7 +78,9 @@ enum {
   HH_BF16X3 = 3,    /* R = hi + lo in BF16, hi*hi + hi*lo + lo*hi on MFMA */
   HH_FP16X3 = 4,    /* R = hi + lo in FP16 (scaled as HH_FP16), three MFMA products */
   HH_FP8E4M3 = 5,   /* OCP e4m3 operands, power-of-two scale per frame and 256 pixels */
-  HH_FP16_STORE = 6 /* hologram stored as FP32 mean + FP16 residual (see above) */
+  HH_FP16_STORE = 6, /* hologram stored as FP32 mean + FP16 residual (see above) */
+  HH_EXACT = 7       /* covariance exactly from the frames (see hh_covariance_frames); FP32
+                        hologram for the projection; nt <= 64; frames 16-byte aligned */
 };
 
 /* How the image of Eq. (7) is evaluated (same result up to rounding). */
@@ -94,7 +100,7 @@ typedef struct {
   int32_t k_lo, k_hi;   /* kept components of I_f (Eq. (6)), 0-based, inclusive,
                            counted in DESCENDING eigenvalue order: 0 <= k_lo <= k_hi < nt.
                            The paper's 1-based ascending n1..n2 maps to nt-n2..nt-n1. */
-  int32_t precision;    /* HH_FP32 ... HH_FP16_STORE (covariance contraction, hologram storage) */
+  int32_t precision;    /* HH_FP32 ... HH_EXACT (covariance contraction, hologram storage) */
   int32_t proj_mode;    /* HH_PROJ_AUTO / _DIRECT / _COMPLEMENT */
   int32_t reserved;     /* must be 0 */
 } hh_params;
@@ -128,6 +134,20 @@ hh_status hh_fresnel(const hh_params *p, const uint16_t *frames, int32_t nframes
  */
 hh_status hh_covariance(const hh_params *p, const float *holo, double *cov,
                         void *workspace, size_t ws_bytes, void *stream);
+
+/*
+ * Step (b) without step (a): C of Eq. (4) computed exactly from the frames as
+ * nx ny I^T I (I[p][t] the uint16 interferograms; exact because Eq. (1) as
+ * discretised is a unit-modulus chirp followed by an unnormalised DFT).  Every
+ * product and partial sum is an integer below 2^53, so the result is exact for
+ * nx ny <= 2^21 (16-bit data) and rounded once per partial beyond; C is real
+ * (imaginary parts written as 0).
+ *   frames : uint16 [nt][ny][nx], 16-byte aligned.   cov : complex128 [nt][nt].
+ *   workspace : at least hh_covariance_workspace_bytes(p) bytes.
+ * Uses nx, ny, nt of *p (nt <= 64).
+ */
+hh_status hh_covariance_frames(const hh_params *p, const uint16_t *frames, double *cov,
+                               void *workspace, size_t ws_bytes, void *stream);
 
 /*
  * Step (c), Eq. (5): Hermitian eigendecomposition C = V Lambda V^{t*} in FP64

@@ -24,6 +24,7 @@ namespace {
 
 typedef float v16f __attribute__((ext_vector_type(16)));
 typedef float v4f __attribute__((ext_vector_type(4)));
+typedef double v4d __attribute__((ext_vector_type(4)));
 
 // Output of accumulator register r on lane l of a 32x32 MFMA block.
 __device__ __forceinline__ int acc_row(int lane, int r) { return 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3); }
@@ -674,6 +675,79 @@ __global__ __launch_bounds__(256) void gram_partial_r16(const h2 *__restrict__ R
   }
 }
 
+
+// Exact covariance from the frames (n_t <= 64): because the input chirp has unit
+// modulus and the unnormalised DFT satisfies F^H F = N_pix I, C = H^H H of Eq. (4)
+// equals N_pix I^T I for the real interferogram matrix I, an integer Gram.  Its
+// products (< 2^32) and sums (< 2^53 up to 2^21 pixels) are exact in FP64, so
+// v_mfma_f64_16x16x4f64 computes it exactly; N_pix is a power of two.  Lane (f, kq)
+// holds frames f + 16 b (b < NB) of the 8 pixels 8 kq .. 8 kq + 7 of each 32-pixel
+// step (one 16-byte load per frame); MFMA step e takes pixel 8 kq + e of every kq.
+// Only the blocks (a, b), a <= b, are accumulated; the rest follow by symmetry.
+template <int NB>
+__global__ __launch_bounds__(256) void gram_partial_u16(const uint16_t *__restrict__ I, int nt, long long npix,
+                                                         int pxw, double npix_d, double *__restrict__ partial) {
+  constexpr int D = NB <= 2 ? 32 : 64;
+  constexpr int NBLK = NB * (NB + 1) / 2;
+  __shared__ double red[D * D];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int f = lane & 15, kq = lane >> 4;
+  const long long p0 = ((long long)blockIdx.x * 4 + wave) * pxw;
+  const uint4 *src[NB];
+  bool valid[NB];
+#pragma unroll
+  for (int b = 0; b < NB; ++b) {
+    valid[b] = 16 * b + f < nt;
+    src[b] = reinterpret_cast<const uint4 *>(I + (long long)(valid[b] ? 16 * b + f : 0) * npix + p0) + kq;
+  }
+  v4d acc[NBLK];
+#pragma unroll
+  for (int q = 0; q < NBLK; ++q) acc[q] = v4d{0.0, 0.0, 0.0, 0.0};
+  const int steps = pxw / 32;
+  for (int j = 0; j < steps; ++j) {
+    const bool in = p0 + 32 * j + 8 * kq < npix;  // npix is a multiple of 8
+    union {
+      uint4 q;
+      unsigned short h[8];
+    } x[NB];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) x[b].q = (valid[b] && in) ? src[b][4 * j] : make_uint4(0u, 0u, 0u, 0u);
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      double v[NB];
+#pragma unroll
+      for (int b = 0; b < NB; ++b) v[b] = (double)x[b].h[e];
+      int q = 0;
+#pragma unroll
+      for (int a = 0; a < NB; ++a)
+#pragma unroll
+        for (int b = a; b < NB; ++b) acc[q++] = __builtin_amdgcn_mfma_f64_16x16x4f64(v[a], v[b], acc[q], 0, 0, 0);
+    }
+  }
+  // fixed-order combination of the four waves (exact: integer-valued doubles), then one store
+  for (int i = tid; i < D * D; i += 256) red[i] = 0.0;
+  __syncthreads();
+  for (int w = 0; w < 4; ++w) {
+    if (wave == w) {
+      int q = 0;
+#pragma unroll
+      for (int a = 0; a < NB; ++a)
+#pragma unroll
+        for (int b = a; b < NB; ++b, ++q)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int i = 16 * a + 4 * kq + r, jj = 16 * b + f;  // 16x16 accumulator layout
+            red[i * D + jj] += acc[q][r];
+            if (a != b) red[jj * D + i] += acc[q][r];
+          }
+    }
+    __syncthreads();
+  }
+  double *out = partial + (size_t)blockIdx.x * partial_len(D);
+  for (int i = tid; i < partial_len(D); i += 256) out[i] = i < D * D ? red[i] * npix_d : 0.0;
+}
+
 // out[g2][l] = sum over g in segment g2 of in[g][l], segments in increasing g.
 __global__ __launch_bounds__(256) void gram_reduce(const double *__restrict__ in, int G, int L, int G2,
                                                    double *__restrict__ out) {
@@ -762,6 +836,22 @@ hipError_t launch_gram_r16(const GramLayout &L, const h2 *r16, const float2 *m, 
   {
     ProfScope ps("gram_partial_r16", s);
     hipLaunchKernelGGL(gram_partial_r16, dim3(L.groups), dim3(256), 0, s, r16, m, nt, npix, L.pxw, inv_s, partial);
+  }
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return gram_tail(L, nt, partial, partial2, cov, s);
+}
+
+hipError_t launch_gram_u16(const GramLayout &L, const uint16_t *frames, int nt, long long npix, double *partial,
+                           double *partial2, double *cov, hipStream_t s) {
+  {
+    ProfScope ps("gram_partial_u16", s);
+    const dim3 g(L.groups), b(256);
+    const double nd = (double)npix;
+    if (nt <= 16) hipLaunchKernelGGL(gram_partial_u16<1>, g, b, 0, s, frames, nt, npix, L.pxw, nd, partial);
+    else if (nt <= 32) hipLaunchKernelGGL(gram_partial_u16<2>, g, b, 0, s, frames, nt, npix, L.pxw, nd, partial);
+    else if (nt <= 48) hipLaunchKernelGGL(gram_partial_u16<3>, g, b, 0, s, frames, nt, npix, L.pxw, nd, partial);
+    else hipLaunchKernelGGL(gram_partial_u16<4>, g, b, 0, s, frames, nt, npix, L.pxw, nd, partial);
   }
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;

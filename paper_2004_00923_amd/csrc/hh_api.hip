@@ -215,13 +215,18 @@ hh_status check_select(const hh_params *p) {
 // from_frames: the entry point starts from frames (hh_pipeline and the batched
 // forms); the FP16 storage form exists only there.
 hh_status check_precision(const hh_params *p, bool from_frames) {
-  if (p->precision < HH_FP32 || p->precision > HH_FP16_STORE)
+  if (p->precision < HH_FP32 || p->precision > HH_EXACT)
     return fail(HH_E_INVALID, "precision=%d unknown", p->precision);
-  if (p->precision != HH_FP32 && p->nt > 32)
+  if (p->precision != HH_FP32 && p->precision != HH_EXACT && p->nt > 32)
     return fail(HH_E_UNSUPPORTED, "precision form %d is built for nt <= 32 (nt=%d)", p->precision, p->nt);
-  if (p->precision == HH_FP16_STORE && !from_frames)
-    return fail(HH_E_UNSUPPORTED, "HH_FP16_STORE applies to entry points that start from frames");
+  if ((p->precision == HH_FP16_STORE || p->precision == HH_EXACT) && !from_frames)
+    return fail(HH_E_UNSUPPORTED, "precision form %d applies to entry points that start from frames", p->precision);
   return HH_OK;
+}
+
+// alignment the frames of one stack need under p's form
+size_t frames_align(const hh_params &p) {
+  return p.precision == HH_EXACT ? 16 : p.precision == HH_FP16_STORE ? 8 : 2;
 }
 
 bool aligned(const void *ptr, size_t a) { return ((uintptr_t)ptr % a) == 0; }
@@ -346,6 +351,7 @@ hipError_t enqueue_front(const hh_params &p, const Plan *pl, const PipeLayout &L
     hipError_t e = launch_fresnel(*pl, tu, frames, p.nt, H, s);
     if (e != hipSuccess) return e;
     v.H = H;
+    if (p.precision == HH_EXACT) return launch_gram_u16(gl, frames, p.nt, npix, part, part2, v.cov, s);
   } else {
     v.H = holo;
   }
@@ -394,7 +400,7 @@ hh_status run_batch(const hh_params *p, int n, const BatchItem *it, void *worksp
       return fail(st, "stack %d: %s", i, msg.c_str());
     }
     if (!it[i].image) return fail(HH_E_INVALID, "stack %d: image must be non-NULL", i);
-    if ((it[i].frames && !aligned(it[i].frames, p[i].precision == HH_FP16_STORE ? 8 : 2)) ||
+    if ((it[i].frames && !aligned(it[i].frames, frames_align(p[i]))) ||
         !aligned(it[i].image, 8) || (it[i].evals && !aligned(it[i].evals, 8)) ||
         (it[i].evecs && !aligned(it[i].evecs, 16)) || (it[i].info && !aligned(it[i].info, 4)))
       return fail(HH_E_INVALID, "stack %d: arrays misaligned", i);
@@ -496,6 +502,27 @@ hh_status hh_covariance(const hh_params *p, const float *holo, double *cov, void
   return HH_OK;
 }
 
+hh_status hh_covariance_frames(const hh_params *p, const uint16_t *frames, double *cov, void *workspace,
+                               size_t ws_bytes, void *stream) {
+  hh_status st;
+  if ((st = check_stack(p))) return st;
+  if (!frames || !cov) return fail(HH_E_INVALID, "frames and cov must be non-NULL");
+  if (!aligned(frames, 16) || !aligned(cov, 16)) return fail(HH_E_INVALID, "frames/cov must be 16-byte aligned");
+  const size_t need = cov_ws_bytes(p);
+  if (!workspace || ws_bytes < need || !aligned(workspace, 256))
+    return fail(HH_E_WORKSPACE, "covariance workspace: need %zu bytes (256-byte aligned), got %zu", need, ws_bytes);
+  const long long npix = (long long)p->nx * p->ny;
+  const GramLayout g = gram_layout(p->nt, npix);
+  hh_params q = *p;
+  q.precision = HH_EXACT;
+  const GramLayout gl = gram_layout(p->nt, npix, get_tune(q).pxw);
+  char *ws = static_cast<char *>(workspace);
+  hipError_t e = launch_gram_u16(gl, frames, p->nt, npix, reinterpret_cast<double *>(ws),
+                                 reinterpret_cast<double *>(ws + align_up(g.partial_bytes)), cov, (hipStream_t)stream);
+  if (e != hipSuccess) return device_fail(e, "hh_covariance_frames");
+  return HH_OK;
+}
+
 hh_status hh_eigh_ex(int32_t nt, const double *cov, double *evals, double *evecs, int32_t *info, int32_t max_sweeps,
                      void *stream) {
   if (nt < 2 || nt > 64) return fail(HH_E_UNSUPPORTED, "nt=%d: must be in [2, 64]", nt);
@@ -559,7 +586,7 @@ hh_status hh_pipeline(const hh_params *p, const uint16_t *frames, float *image, 
   if ((st = check_optics(p)) || (st = check_stack(p)) || (st = check_select(p)) || (st = check_precision(p, true)))
     return st;
   if (!frames || !image) return fail(HH_E_INVALID, "frames and image must be non-NULL");
-  if (!aligned(frames, p->precision == HH_FP16_STORE ? 8 : 2) || !aligned(image, 8) || (evals && !aligned(evals, 8)) ||
+  if (!aligned(frames, frames_align(*p)) || !aligned(image, 8) || (evals && !aligned(evals, 8)) ||
       (evecs && !aligned(evecs, 16)) || (info && !aligned(info, 4)))
     return fail(HH_E_INVALID, "pipeline arrays misaligned");
   const PipeLayout L = pipe_layout(p);

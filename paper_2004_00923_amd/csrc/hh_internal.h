@@ -74,6 +74,9 @@ GramLayout gram_layout(int nt, long long npix, int pxw = kGramPxwMin);
 // larger stacks use the FP32 form).
 hipError_t launch_gram(const GramLayout &L, const float2 *holo, int nt, long long npix,
                        double *partial, double *partial2, double *cov, hipStream_t s, int precision = HH_FP32);
+// Exact covariance from the frames, C = N_pix I^T I (n_t <= 64; frames 16-byte aligned).
+hipError_t launch_gram_u16(const GramLayout &L, const uint16_t *frames, int nt, long long npix, double *partial,
+                           double *partial2, double *cov, hipStream_t s);
 // FP16 storage form: H = m 1^T + r16 / s with inv_s = 1 / s (n_t <= 32).
 hipError_t launch_gram_r16(const GramLayout &L, const h2 *r16, const float2 *m, int nt, long long npix, float inv_s,
                            double *partial, double *partial2, double *cov, hipStream_t s);

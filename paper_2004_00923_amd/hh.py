@@ -16,11 +16,11 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libhh.so")
 
 HH_OK, HH_E_INVALID, HH_E_UNSUPPORTED, HH_E_WORKSPACE, HH_E_DEVICE, HH_E_NOT_CONVERGED = range(6)
-HH_FP32, HH_BF16, HH_FP16, HH_BF16X3, HH_FP16X3, HH_FP8E4M3, HH_FP16_STORE = range(7)
+HH_FP32, HH_BF16, HH_FP16, HH_BF16X3, HH_FP16X3, HH_FP8E4M3, HH_FP16_STORE, HH_EXACT = range(8)
 HH_PROJ_AUTO, HH_PROJ_DIRECT, HH_PROJ_COMPLEMENT = range(3)
 
 PRECISIONS = {"fp32": HH_FP32, "bf16": HH_BF16, "fp16": HH_FP16, "bf16x3": HH_BF16X3,
-              "fp16x3": HH_FP16X3, "fp8e4m3": HH_FP8E4M3, "fp16store": HH_FP16_STORE}
+              "fp16x3": HH_FP16X3, "fp8e4m3": HH_FP8E4M3, "fp16store": HH_FP16_STORE, "exact": HH_EXACT}
 
 
 class hh_params(ctypes.Structure):
@@ -91,6 +91,7 @@ SIGNATURES = {
     "hh_covariance_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(hh_params)]),
     "hh_fresnel": (ctypes.c_int32, [ctypes.POINTER(hh_params), _P, ctypes.c_int32, _P, _P]),
     "hh_covariance": (ctypes.c_int32, [ctypes.POINTER(hh_params), _P, _P, _P, ctypes.c_size_t, _P]),
+    "hh_covariance_frames": (ctypes.c_int32, [ctypes.POINTER(hh_params), _P, _P, _P, ctypes.c_size_t, _P]),
     "hh_eigh": (ctypes.c_int32, [ctypes.c_int32, _P, _P, _P, _P, _P]),
     "hh_eigh_ex": (ctypes.c_int32, [ctypes.c_int32, _P, _P, _P, _P, ctypes.c_int32, _P]),
     "hh_project_render": (ctypes.c_int32, [ctypes.POINTER(hh_params), _P, _P, _P, _P]),
@@ -189,6 +190,16 @@ def hh_covariance(p: Params, holo, cov, workspace, stream=None):
     _dev_tensor(cov, torch.complex128, (p.nt, p.nt), "cov")
     _check(lib().hh_covariance(ctypes.byref(p.c()), _ptr(holo), _ptr(cov), _ptr(workspace),
                                workspace.numel() * workspace.element_size(), _stream(stream)))
+    return cov
+
+
+def hh_covariance_frames(p: Params, frames, cov, workspace, stream=None):
+    """C = nx ny I^T I exactly from the uint16 frames; see include/hh.h."""
+    import torch
+    _dev_tensor(frames, torch.uint16, (p.nt, p.ny, p.nx), "frames")
+    _dev_tensor(cov, torch.complex128, (p.nt, p.nt), "cov")
+    _check(lib().hh_covariance_frames(ctypes.byref(p.c()), _ptr(frames), _ptr(cov), _ptr(workspace),
+                                      workspace.numel() * workspace.element_size(), _stream(stream)))
     return cov
 
 

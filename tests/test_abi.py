@@ -107,12 +107,24 @@ def test_precision_form_validation():
         st = L.hh_covariance(ctypes.byref(p), ctypes.c_void_p(16), ctypes.c_void_p(16), ctypes.c_void_p(256),
                              1, None)
         assert st == hh.HH_E_UNSUPPORTED
-    # the FP16 storage form starts from frames: entry points taking FP32 holograms reject it
+    # the FP16 storage and exact forms start from frames: entry points taking FP32 holograms reject them
+    for prec in (hh.HH_FP16_STORE, hh.HH_EXACT):
+        p = hh.Params(nx=64, ny=64, nt=8, k_lo=1, k_hi=7, precision=prec).c()
+        assert L.hh_covariance(ctypes.byref(p), ctypes.c_void_p(16), ctypes.c_void_p(16), ctypes.c_void_p(256),
+                               1, None) == hh.HH_E_UNSUPPORTED
+        assert L.hh_project_render(ctypes.byref(p), ctypes.c_void_p(16), ctypes.c_void_p(16),
+                                   ctypes.c_void_p(16), None) == hh.HH_E_UNSUPPORTED
+    # the exact form takes stacks up to 64 frames and needs 16-byte aligned frames
+    p = hh.Params(nx=64, ny=64, nt=64, k_lo=1, k_hi=7, precision=hh.HH_EXACT).c()
+    assert L.hh_pipeline(ctypes.byref(p), ctypes.c_void_p(256), ctypes.c_void_p(16), None, None, None,
+                         ctypes.c_void_p(256), 1, None) == hh.HH_E_WORKSPACE
+    assert L.hh_pipeline(ctypes.byref(p), ctypes.c_void_p(264), ctypes.c_void_p(16), None, None, None,
+                         ctypes.c_void_p(256), 1, None) == hh.HH_E_INVALID
+    assert L.hh_covariance_frames(ctypes.byref(p), ctypes.c_void_p(8), ctypes.c_void_p(16), ctypes.c_void_p(256),
+                                  1 << 30, None) == hh.HH_E_INVALID
+    assert L.hh_covariance_frames(ctypes.byref(p), ctypes.c_void_p(16), ctypes.c_void_p(16), ctypes.c_void_p(256),
+                                  1, None) == hh.HH_E_WORKSPACE
     p = hh.Params(nx=64, ny=64, nt=8, k_lo=1, k_hi=7, precision=hh.HH_FP16_STORE).c()
-    assert L.hh_covariance(ctypes.byref(p), ctypes.c_void_p(16), ctypes.c_void_p(16), ctypes.c_void_p(256),
-                           1, None) == hh.HH_E_UNSUPPORTED
-    assert L.hh_project_render(ctypes.byref(p), ctypes.c_void_p(16), ctypes.c_void_p(16), ctypes.c_void_p(16),
-                               None) == hh.HH_E_UNSUPPORTED
     st = L.hh_pipeline(ctypes.byref(p), ctypes.c_void_p(16), ctypes.c_void_p(16), None, None, None,
                        ctypes.c_void_p(256), 1, None)
     assert st == hh.HH_E_WORKSPACE
