@@ -110,6 +110,8 @@ def main():
                     help="stacks per step, processed by one hh_pipeline_batch call (1 = hh_pipeline)")
     ap.add_argument("--precision", default="fp32",
                     help="arithmetic of the covariance contraction: fp32, bf16, fp16, bf16x3, fp16x3, fp8e4m3")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the default launch choices instead of running the autotuner first (untimed)")
     ap.add_argument("--workload", default="stack", choices=["stack", "batched8", "serve"],
                     help="stack: the 1024^2 x 32 headline; batched8: 8 uneven stacks replayed as one HIP graph; "
                          "serve: two simulated cameras through the streaming server")
@@ -150,6 +152,10 @@ def main():
     p = hh.Params(nx=NX, ny=NY, nt=NT, k_lo=K_LO, k_hi=K_HI, precision=hh.PRECISIONS[args.precision])
     B = max(1, args.batch)
     ws1 = hh.alloc_workspace(hh.workspace_bytes(p), dev)
+    tuning = hh.tuning_get(p)
+    if not args.no_autotune:
+        print("bench: autotuning launch choices (untimed)", file=sys.stderr, flush=True)
+        tuning = hh.autotune(p, frames[0], ws1, reps=5)
     img1 = torch.empty((NY, NX), dtype=torch.float32, device=dev)
     info = torch.empty(1, dtype=torch.int32, device=dev)
     if B > 1:
@@ -242,7 +248,7 @@ def main():
         "config": {"workload": "one 32x1024x1024 uint16 stack per step (4 seeded stacks rotated), "
                                f"lambda 785 nm, pitch 20 um, z 0.3 m, PCs 2..31, {args.precision}",
                    "stacks_per_s": value / NT, "precision": args.precision, "jacobi_sweeps": sweeps,
-                   "stacks_per_step": B, "ms_per_stack": ms_per_step / B},
+                   "stacks_per_step": B, "ms_per_stack": ms_per_step / B, "tuning": tuning},
         "roofline": roofline,
         "stack_roofline": {"bytes_per_stack": sb,
                            "achieved": sb * B / (ms_per_step * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,

@@ -80,7 +80,7 @@ enum {
   HH_FP8E4M3 = 5,   /* OCP e4m3 operands, power-of-two scale per frame and 256 pixels */
   HH_FP16_STORE = 6, /* hologram stored as FP32 mean + FP16 residual (see above) */
   HH_EXACT = 7       /* covariance exactly from the frames (see hh_covariance_frames); FP32
-                        hologram for the projection; nt <= 64; frames 16-byte aligned */
+                        hologram for the projection; nt <= 64 */
 };
 
 /* How the image of Eq. (7) is evaluated (same result up to rounding). */
@@ -113,7 +113,8 @@ size_t hh_covariance_workspace_bytes(const hh_params *p);
 
 /*
  * Step (a), Eq. (1): Fresnel holograms of `nframes` frames.
- *   frames : uint16 [nframes][ny][nx] raw interferograms (no offset removed).
+ *   frames : uint16 [nframes][ny][nx] raw interferograms (no offset removed),
+ *            16-byte aligned.
  *   holo   : complex64 [nframes][ny][nx] output,
  *            holo[t][v][u] = sum_{n,m} I_t[n][m] c[n][m] exp(-2 pi i (u m/nx + v n/ny)),
  *            c[n][m] = exp(-i pi d^2 ((m - nx/2)^2 + (n - ny/2)^2) / (lambda z)).
@@ -198,7 +199,7 @@ hh_status hh_svd_filter(const hh_params *p, const float *holo, const double *eve
 
 /*
  * Steps (a)-(e) on one stack, in the paper's order, all on `stream`.
- *   frames : uint16 [nt][ny][nx].
+ *   frames : uint16 [nt][ny][nx], 16-byte aligned.
  *   image  : float32 [ny][nx] output (Eq. (7)).
  *   evals, evecs, info : optional outputs as in hh_eigh (NULL = not returned).
  *   workspace : at least hh_workspace_bytes(p) bytes; holds the hologram stack
@@ -211,7 +212,7 @@ hh_status hh_pipeline(const hh_params *p, const uint16_t *frames, float *image,
 
 /* One stack of a batch: its input, its image and optional eigen-outputs. */
 typedef struct {
-  const uint16_t *frames; /* uint16 [nt][ny][nx] */
+  const uint16_t *frames; /* uint16 [nt][ny][nx], 16-byte aligned */
   float *image;           /* float32 [ny][nx] output */
   double *evals;          /* float64 [nt] output, or NULL */
   double *evecs;          /* complex128 [nt][nt] output, or NULL */

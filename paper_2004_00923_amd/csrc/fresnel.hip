@@ -60,8 +60,56 @@ __global__ __launch_bounds__(ROWS *(N / fft_e(N, EP))) void fresnel_rows(
   const size_t mbase = (size_t)(live ? row : 0) * N;
 
   float2 v[E];
-  {
-    const float2 cy = chirp_y[live ? row : 0];
+  const float2 cy = chirp_y[live ? row : 0];
+  if constexpr (FftCfg<N, EP>::P > 1) {
+    __shared__ float2 lds[ROWS * FftCfg<N, EP>::LDSN];
+    // The row arrives through LDS: 16-byte coalesced loads of 8 pixels each are
+    // written to the row's LDS area as floats, then every thread reads its
+    // elements t + T i in FFT order (the FFT's first pass then reuses the area).
+    float *stage = reinterpret_cast<float *>(lds + r * FftCfg<N, EP>::LDSN);
+#pragma unroll
+    for (int c = t; c < N / 8; c += T) {
+      float x[8];
+      if (live) {
+        if constexpr (IN == kInF32) {
+          const float4 *s4 = reinterpret_cast<const float4 *>(static_cast<const float *>(src) + base) + 2 * c;
+          const float4 a = s4[0], b = s4[1];
+          x[0] = a.x; x[1] = a.y; x[2] = a.z; x[3] = a.w;
+          x[4] = b.x; x[5] = b.y; x[6] = b.z; x[7] = b.w;
+        } else {
+          union {
+            uint4 q;
+            uint16_t h[8];
+          } u;
+          u.q = reinterpret_cast<const uint4 *>(static_cast<const uint16_t *>(src) + base)[c];
+#pragma unroll
+          for (int e = 0; e < 8; ++e) x[e] = (float)u.h[e];
+          if constexpr (IN == kInU16MinusMean) {
+            const float4 *m4 = reinterpret_cast<const float4 *>(mean + mbase) + 2 * c;
+            const float4 a = m4[0], b = m4[1];
+            x[0] -= a.x; x[1] -= a.y; x[2] -= a.z; x[3] -= a.w;
+            x[4] -= b.x; x[5] -= b.y; x[6] -= b.z; x[7] -= b.w;
+          }
+        }
+      } else {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) x[e] = 0.0f;
+      }
+      float2 *d2 = reinterpret_cast<float2 *>(stage + 8 * c);  // rows start 8-byte aligned in LDS
+#pragma unroll
+      for (int e = 0; e < 4; ++e) d2[e] = make_float2(x[2 * e], x[2 * e + 1]);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < E; ++i) {
+      const int m = t + T * i;
+      const float val = stage[m];
+      const float2 c = cmul(chirp_x[m], cy);
+      v[i] = make_float2(val * c.x, val * c.y);
+    }
+    __syncthreads();
+    fft_passes<N, EP, 0>(v, t, tw, lds + r * FftCfg<N, EP>::LDSN, RowSlot{});
+  } else {
 #pragma unroll
     for (int i = 0; i < E; ++i) {
       const int m = t + T * i;
@@ -77,11 +125,6 @@ __global__ __launch_bounds__(ROWS *(N / fft_e(N, EP))) void fresnel_rows(
       const float2 c = cmul(chirp_x[m], cy);
       v[i] = make_float2(val * c.x, val * c.y);
     }
-  }
-  if constexpr (FftCfg<N, EP>::P > 1) {
-    __shared__ float2 lds[ROWS * FftCfg<N, EP>::LDSN];
-    fft_passes<N, EP, 0>(v, t, tw, lds + r * FftCfg<N, EP>::LDSN, RowSlot{});
-  } else {
     fft_passes<N, EP, 0>(v, t, tw, (float2 *)nullptr, RowSlot{});
   }
   if (live) {

@@ -31,6 +31,8 @@ __device__ __forceinline__ int acc_row(int lane, int r) { return 8 * (r >> 2) + 
 
 // Length (doubles) of one workgroup partial: S, Q (D x D each), a (re, im), m^H m, pad.
 __host__ __device__ constexpr int partial_len(int D) { return 2 * D * D + 2 * D + 2; }
+// second-level partial count (the first level is summed in this many segments)
+constexpr int kGroups2 = 16;
 
 template <int CTRL>
 __device__ __forceinline__ float dpp(float v) {
@@ -722,7 +724,7 @@ __global__ __launch_bounds__(256) void gram_partial_u16(const uint16_t *__restri
 #pragma unroll
       for (int a = 0; a < NB; ++a)
 #pragma unroll
-        for (int b = a; b < NB; ++b) acc[q++] = __builtin_amdgcn_mfma_f64_16x16x4f64(v[a], v[b], acc[q], 0, 0, 0);
+        for (int b = a; b < NB; ++b, ++q) acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(v[a], v[b], acc[q], 0, 0, 0);
     }
   }
   // fixed-order combination of the four waves (exact: integer-valued doubles), then one store
@@ -737,7 +739,8 @@ __global__ __launch_bounds__(256) void gram_partial_u16(const uint16_t *__restri
         for (int b = a; b < NB; ++b, ++q)
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
-            const int i = 16 * a + 4 * kq + r, jj = 16 * b + f;  // 16x16 accumulator layout
+            // FP64 16x16 accumulator layout: register r of lane (f, kq) holds row kq + 4 r, column f
+            const int i = 16 * a + kq + 4 * r, jj = 16 * b + f;
             red[i * D + jj] += acc[q][r];
             if (a != b) red[jj * D + i] += acc[q][r];
           }
@@ -771,8 +774,9 @@ __global__ __launch_bounds__(256) void gram_finalize(const double *__restrict__ 
   const int s = e / nt, t = e % nt;
   const int lo = s < t ? s : t, hi = s < t ? t : s;
   double re = 0.0, qst = 0.0, qts = 0.0, mm = 0.0, alo = 0.0, ahi = 0.0, ais = 0.0, ait = 0.0;
-#pragma unroll 4
-  for (int g = 0; g < G2; ++g) {
+#pragma unroll
+  for (int g = 0; g < kGroups2; ++g) {  // all loads in flight at once
+    if (g >= G2) break;
     const double *p = in2 + g * L;
     re += p[lo * D + hi];
     qst += p[(size_t)D * D + s * D + t];
@@ -795,7 +799,7 @@ GramLayout gram_layout(int nt, long long npix, int pxw) {
   L.pxw = pxw;
   L.chunks = (npix + pxw - 1) / pxw;  // one chunk per wave
   L.groups = (int)((L.chunks + 3) / 4);
-  L.groups2 = L.groups < 16 ? L.groups : 16;
+  L.groups2 = L.groups < kGroups2 ? L.groups : kGroups2;
   L.partial_bytes = (size_t)L.groups * partial_len(L.D) * sizeof(double);
   L.partial2_bytes = (size_t)L.groups2 * partial_len(L.D) * sizeof(double);
   return L;

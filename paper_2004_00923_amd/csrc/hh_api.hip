@@ -225,9 +225,7 @@ hh_status check_precision(const hh_params *p, bool from_frames) {
 }
 
 // alignment the frames of one stack need under p's form
-size_t frames_align(const hh_params &p) {
-  return p.precision == HH_EXACT ? 16 : p.precision == HH_FP16_STORE ? 8 : 2;
-}
+size_t frames_align(const hh_params &) { return 16; }  // 16-byte loads of 8 pixels
 
 bool aligned(const void *ptr, size_t a) { return ((uintptr_t)ptr % a) == 0; }
 
@@ -473,7 +471,7 @@ hh_status hh_fresnel(const hh_params *p, const uint16_t *frames, int32_t nframes
   if (nframes < 0 || nframes > 65535) return fail(HH_E_INVALID, "nframes=%d must be in [0, 65535]", nframes);
   if (nframes == 0) return HH_OK;
   if (!frames || !holo) return fail(HH_E_INVALID, "frames and holo must be non-NULL");
-  if (!aligned(frames, 2) || !aligned(holo, 16)) return fail(HH_E_INVALID, "frames/holo misaligned");
+  if (!aligned(frames, 16) || !aligned(holo, 16)) return fail(HH_E_INVALID, "frames/holo must be 16-byte aligned");
   const Plan *pl = get_plan(*p);
   if (!pl) return HH_E_DEVICE;
   hipError_t e =
@@ -618,7 +616,7 @@ hh_status hh_pipeline_batch(const hh_params *p, int32_t n, const hh_stack *stack
   std::vector<BatchItem> items(n);
   for (int i = 0; i < n; ++i) {
     if (!stacks[i].frames) return fail(HH_E_INVALID, "stack %d: frames must be non-NULL", i);
-    if (!aligned(stacks[i].frames, 2)) return fail(HH_E_INVALID, "stack %d: frames misaligned", i);
+    if (!aligned(stacks[i].frames, 16)) return fail(HH_E_INVALID, "stack %d: frames must be 16-byte aligned", i);
     items[i] = BatchItem{stacks[i].frames, nullptr, stacks[i].image, stacks[i].evals, stacks[i].evecs, stacks[i].info};
   }
   return run_batch(p, n, items.data(), workspace, ws_bytes, (hipStream_t)stream, "hh_pipeline_batch");
@@ -653,7 +651,7 @@ hh_status hh_graph_create(const hh_params *p, int32_t n, const hh_stack *stacks,
   std::vector<BatchItem> items(n);
   for (int i = 0; i < n; ++i) {
     if (!stacks[i].frames) return fail(HH_E_INVALID, "stack %d: frames must be non-NULL", i);
-    if (!aligned(stacks[i].frames, 2)) return fail(HH_E_INVALID, "stack %d: frames misaligned", i);
+    if (!aligned(stacks[i].frames, 16)) return fail(HH_E_INVALID, "stack %d: frames must be 16-byte aligned", i);
     items[i] = BatchItem{stacks[i].frames, nullptr, stacks[i].image, stacks[i].evals, stacks[i].evecs, stacks[i].info};
     hh_status st;
     if ((st = check_optics(p + i)) || (st = check_shape(p + i))) {

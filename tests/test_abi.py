@@ -63,6 +63,8 @@ def test_null_and_counts():
     assert _call_fresnel(p, -1) == hh.HH_E_INVALID
     assert _call_fresnel(p, 0) == hh.HH_OK          # empty stack: nothing to do
     assert L.hh_fresnel(ctypes.byref(p), ctypes.c_void_p(16), 1, ctypes.c_void_p(12), None) == hh.HH_E_INVALID
+    # frames are read with 16-byte loads
+    assert L.hh_fresnel(ctypes.byref(p), ctypes.c_void_p(24), 1, ctypes.c_void_p(16), None) == hh.HH_E_INVALID
 
 
 @pytest.mark.parametrize("k_lo,k_hi,nt,status", [

@@ -37,7 +37,7 @@ def test_covariance_frames_bit_exact(hh, nt, ny, nx):
     C = torch.empty((nt, nt), dtype=torch.complex128, device="cuda")
     hh.hh_covariance_frames(p, to_dev(f), C, ws)
     got = to_np(C)
-    want = (_integer_gram(f) * (nx * ny)).astype(np.float64)   # exact: a power of two times an integer < 2^53
+    want = _integer_gram(f).astype(np.float64) * (nx * ny)   # exact: an integer < 2^53 times a power of two
     say(f"covariance_frames {nt}x{ny}x{nx}: max |diff| {np.abs(got.real - want).max():.1e}")
     assert np.array_equal(got.real, want)
     assert np.all(got.imag == 0.0)
