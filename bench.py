@@ -35,7 +35,8 @@ PAPER_INTERFEROGRAMS_PER_S = 20 * 32  # PCA of 32-frame stacks "up to 20 times p
 # of the stack it works on.  Fresnel row pass: reads the uint16 frame (2) and
 # writes complex64 (8), plus the float mean frame (4 per pixel) in the FP16
 # storage form; column pass: reads 8 and writes 8 in place (FP32) or 4 (FP16
-# residual); Gram: reads the hologram (8, or 4 + the complex64 mean per pixel);
+# residual); Gram: reads the hologram (8, or 4 + the complex64 mean per pixel, or
+# the 2-byte frames for the exact form);
 # projection: the same reads plus the float32 image (4 per pixel); frame_mean:
 # reads the frames once and writes the float mean.
 KERNEL_BYTES = {
@@ -46,6 +47,7 @@ KERNEL_BYTES = {
     "gram_partial": (8.0, 0.0),
     "gram_partial_lp": (8.0, 0.0),
     "gram_partial_r16": (4.0, 8.0),
+    "gram_partial_u16": (2.0, 0.0),
     "project_complement": (8.0, 4.0),
     "project_direct": (8.0, 4.0),
     "project_r16_complement": (4.0, 12.0),
@@ -72,6 +74,8 @@ def stack_bytes(precision: str) -> int:
     npf, npx = NT * NY * NX, NY * NX
     if precision == "fp16store":
         return npf * (2 + 2 + 3 * 4) + npx * (4 + 4 + 3 * 8 + 4)
+    if precision == "exact":   # covariance from the frames: input read twice, hologram written and read once
+        return npf * (2 + 2 + 2 * 8) + 4 * npx
     return npf * (2 + 3 * 8) + 4 * npx
 
 
@@ -112,6 +116,8 @@ def main():
                     help="arithmetic of the covariance contraction: fp32, bf16, fp16, bf16x3, fp16x3, fp8e4m3")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default launch choices instead of running the autotuner first (untimed)")
+    ap.add_argument("--tuning", default=None,
+                    help="pin the launch choices 'rows,cols,pxw,group' (no autotuning), e.g. 2,0,512,0")
     ap.add_argument("--workload", default="stack", choices=["stack", "batched8", "serve"],
                     help="stack: the 1024^2 x 32 headline; batched8: 8 uneven stacks replayed as one HIP graph; "
                          "serve: two simulated cameras through the streaming server")
@@ -153,7 +159,11 @@ def main():
     B = max(1, args.batch)
     ws1 = hh.alloc_workspace(hh.workspace_bytes(p), dev)
     tuning = hh.tuning_get(p)
-    if not args.no_autotune:
+    if args.tuning:
+        r, c, x, g = (int(v) for v in args.tuning.split(","))
+        hh.tuning_set(p, fft_rows=r, fft_cols=c, gram_pxw=x, group=g)
+        tuning = hh.tuning_get(p)
+    elif not args.no_autotune:
         print("bench: autotuning launch choices (untimed)", file=sys.stderr, flush=True)
         tuning = hh.autotune(p, frames[0], ws1, reps=5)
     img1 = torch.empty((NY, NX), dtype=torch.float32, device=dev)

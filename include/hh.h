@@ -290,15 +290,23 @@ void hh_graph_destroy(hh_graph *g);
  *   fft_rows : row-FFT launch shape: 0 = 16 points per thread, 256-thread groups;
  *              1 = 32 points per thread, 256-thread groups; 2 = 32 points per
  *              thread, 2 rows per group; 3 = 16 points per thread, one row per
- *              group.  Shapes 1-3 exist for nx >= 512.
+ *              group; 4 and 5 = shapes 2 and 0 exchanging real and imaginary parts
+ *              separately through half the LDS; 6 and 7 = shapes 3 and 2 as a
+ *              persistent grid (eight one-wave groups per compute unit) that loads
+ *              the next row while transforming the current one.  Shapes 1-7 exist for
+ *              nx >= 512.
  *   fft_cols : column-FFT launch shape: 0 = 16 points per thread, 16 columns per
  *              group (fewer where the LDS does not hold them); 1 = 16 points, half
- *              as many columns; 2 = 32 points per thread.  Shapes 1-2 exist for
- *              ny >= 512.
+ *              as many columns; 2 = 32 points per thread; 3 and 4 = shapes 0 and 2
+ *              with the split exchange; 5 and 6 = shapes 0 and 3 as a persistent grid
+ *              (one group per compute unit) that loads the next strip while
+ *              transforming the current one.
+ *              Shapes 1-6 exist for ny >= 512.
  *   gram_pxw : covariance split-K chunk, pixels per wavefront: 256, 512 or 1024
  *              (FP32 partial sums grow with it).
  *   group    : frames per Fresnel group (row pass then column pass), 0 = about
- *              64 MiB of FP32 holograms, at most that.
+ *              64 MiB of FP32 holograms, at most four times that (the FP16
+ *              storage form clamps it to the default, the size of its buffer).
  * The FFT choices and the group apply to every call with the same (nx, ny) on
  * the current device, gram_pxw to the same (nx * ny, nt, precision).
  */

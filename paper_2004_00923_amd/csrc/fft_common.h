@@ -115,9 +115,12 @@ struct FftCfg {
 // sequence entering pass P; on return v[i] = X[t + T*i] (natural order).
 // slot(e) maps a logical element of this transform to its LDS slot; every
 // thread of the workgroup must call this (it contains barriers).
-template <int N, int EP, int P, class Slot>
+// SPLIT = false: lds holds float2 slots and each exchange moves whole complex
+// values.  SPLIT = true: lds holds float slots (half the LDS) and each exchange
+// moves the real parts, then the imaginary parts.
+template <int N, int EP, int P, bool SPLIT = false, class Slot, class L>
 __device__ __forceinline__ void fft_passes(float2 (&v)[fft_e(N, EP)], int t, const float2 *__restrict__ tw,
-                                           float2 *lds, Slot slot) {
+                                           L *lds, Slot slot) {
   constexpr int E = FftCfg<N, EP>::E, T = FftCfg<N, EP>::T;
   constexpr int R = fft_radix(N, E, P), NS = fft_ns(N, E, P), B = E / R;
   constexpr bool last = (P == FftCfg<N, EP>::P - 1);
@@ -133,7 +136,7 @@ __device__ __forceinline__ void fft_passes(float2 (&v)[fft_e(N, EP)], int t, con
       for (int k = 1; k < R; ++k) u[k] = cmul(u[k], tw[jm * k * (N / (NS * R))]);
     }
     dft_reg<R>(u);
-    if constexpr (last) {
+    if constexpr (last || SPLIT) {
 #pragma unroll
       for (int k = 0; k < R; ++k) v[b + B * k] = u[k];
     } else {
@@ -143,11 +146,36 @@ __device__ __forceinline__ void fft_passes(float2 (&v)[fft_e(N, EP)], int t, con
     }
   }
   if constexpr (!last) {
-    __syncthreads();
+    if constexpr (SPLIT) {
+      // element (b, k) of this pass goes to logical position base(b) + k NS
 #pragma unroll
-    for (int i = 0; i < E; ++i) v[i] = lds[slot(t + T * i)];
-    if constexpr (P + 1 < FftCfg<N, EP>::P - 1) __syncthreads();  // reads done before the next pass writes
-    fft_passes<N, EP, P + 1>(v, t, tw, lds, slot);
+      for (int half = 0; half < 2; ++half) {
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+          const int j = t + T * b;
+          const int base = (j / NS) * NS * R + (j & (NS - 1));
+#pragma unroll
+          for (int k = 0; k < R; ++k) lds[slot(base + k * NS)] = half ? v[b + B * k].y : v[b + B * k].x;
+        }
+        __syncthreads();
+        float w[E];
+#pragma unroll
+        for (int i = 0; i < E; ++i) w[i] = lds[slot(t + T * i)];
+        __syncthreads();  // reads done before the next writes
+#pragma unroll
+        for (int i = 0; i < E; ++i) {
+          if (half) v[i].y = w[i];
+          else v[i].x = w[i];
+        }
+      }
+      fft_passes<N, EP, P + 1, SPLIT>(v, t, tw, lds, slot);
+    } else {
+      __syncthreads();
+#pragma unroll
+      for (int i = 0; i < E; ++i) v[i] = lds[slot(t + T * i)];
+      if constexpr (P + 1 < FftCfg<N, EP>::P - 1) __syncthreads();  // reads done before the next pass writes
+      fft_passes<N, EP, P + 1, SPLIT>(v, t, tw, lds, slot);
+    }
   }
 }
 

@@ -10,6 +10,8 @@
 // (1024 = 16 * 16 * 4: one wave per 1024-point row, 128-byte coalesced uint16
 // loads), register DFTs, LDS exchanges between passes, and W_N twiddles from a
 // table built in FP64 on the host.
+#include <type_traits>
+
 #include "fft_common.h"
 #include "hh_internal.h"
 
@@ -47,7 +49,7 @@ struct ColSlot {
 // (the stack's temporal mean), or one float frame.
 enum { kInU16 = 0, kInU16MinusMean = 1, kInF32 = 2 };
 
-template <int N, int EP, int ROWS, int IN>
+template <int N, int EP, int ROWS, int IN, bool SPLIT>
 __global__ __launch_bounds__(ROWS *(N / fft_e(N, EP))) void fresnel_rows(
     const void *__restrict__ src, const float *__restrict__ mean, int ny, const float2 *__restrict__ chirp_x,
     const float2 *__restrict__ chirp_y, const float2 *__restrict__ tw, float2 *__restrict__ out) {
@@ -62,7 +64,8 @@ __global__ __launch_bounds__(ROWS *(N / fft_e(N, EP))) void fresnel_rows(
   float2 v[E];
   const float2 cy = chirp_y[live ? row : 0];
   if constexpr (FftCfg<N, EP>::P > 1) {
-    __shared__ float2 lds[ROWS * FftCfg<N, EP>::LDSN];
+    typedef typename std::conditional<SPLIT, float, float2>::type Slot;
+    __shared__ Slot lds[ROWS * FftCfg<N, EP>::LDSN];
     // The row arrives through LDS: 16-byte coalesced loads of 8 pixels each are
     // written to the row's LDS area as floats, then every thread reads its
     // elements t + T i in FFT order (the FFT's first pass then reuses the area).
@@ -95,9 +98,8 @@ __global__ __launch_bounds__(ROWS *(N / fft_e(N, EP))) void fresnel_rows(
 #pragma unroll
         for (int e = 0; e < 8; ++e) x[e] = 0.0f;
       }
-      float2 *d2 = reinterpret_cast<float2 *>(stage + 8 * c);  // rows start 8-byte aligned in LDS
 #pragma unroll
-      for (int e = 0; e < 4; ++e) d2[e] = make_float2(x[2 * e], x[2 * e + 1]);
+      for (int e = 0; e < 8; ++e) stage[8 * c + e] = x[e];
     }
     __syncthreads();
 #pragma unroll
@@ -108,7 +110,7 @@ __global__ __launch_bounds__(ROWS *(N / fft_e(N, EP))) void fresnel_rows(
       v[i] = make_float2(val * c.x, val * c.y);
     }
     __syncthreads();
-    fft_passes<N, EP, 0>(v, t, tw, lds + r * FftCfg<N, EP>::LDSN, RowSlot{});
+    fft_passes<N, EP, 0, SPLIT>(v, t, tw, lds + r * FftCfg<N, EP>::LDSN, RowSlot{});
   } else {
 #pragma unroll
     for (int i = 0; i < E; ++i) {
@@ -125,7 +127,7 @@ __global__ __launch_bounds__(ROWS *(N / fft_e(N, EP))) void fresnel_rows(
       const float2 c = cmul(chirp_x[m], cy);
       v[i] = make_float2(val * c.x, val * c.y);
     }
-    fft_passes<N, EP, 0>(v, t, tw, (float2 *)nullptr, RowSlot{});
+    fft_passes<N, EP, 0, false>(v, t, tw, (float2 *)nullptr, RowSlot{});
   }
   if (live) {
 #pragma unroll
@@ -135,7 +137,7 @@ __global__ __launch_bounds__(ROWS *(N / fft_e(N, EP))) void fresnel_rows(
 
 // R16: instead of writing the column FFT back in place, write it scaled by
 // `scale` and rounded to FP16 (round to nearest even) into r16 [frames][N][nx].
-template <int N, int EP, int W, bool R16>
+template <int N, int EP, int W, bool R16, bool SPLIT>
 __global__ __launch_bounds__(W *(N / fft_e(N, EP))) void fresnel_cols(float2 *__restrict__ data, int nx,
                                                                const float2 *__restrict__ tw, h2 *__restrict__ r16,
                                                                float scale) {
@@ -151,10 +153,11 @@ __global__ __launch_bounds__(W *(N / fft_e(N, EP))) void fresnel_cols(float2 *__
 #pragma unroll
   for (int i = 0; i < E; ++i) v[i] = live ? base[(size_t)(t + T * i) * nx] : make_float2(0.f, 0.f);
   if constexpr (FftCfg<N, EP>::P > 1) {
-    __shared__ float2 lds[W * FftCfg<N, EP>::LDSN];
-    fft_passes<N, EP, 0>(v, t, tw, lds, ColSlot<W>{c});
+    typedef typename std::conditional<SPLIT, float, float2>::type Slot;
+    __shared__ Slot lds[W * FftCfg<N, EP>::LDSN];
+    fft_passes<N, EP, 0, SPLIT>(v, t, tw, lds, ColSlot<W>{c});
   } else {
-    fft_passes<N, EP, 0>(v, t, tw, (float2 *)nullptr, ColSlot<W>{c});
+    fft_passes<N, EP, 0, false>(v, t, tw, (float2 *)nullptr, ColSlot<W>{c});
   }
   if (live) {
     if constexpr (R16) {
@@ -170,6 +173,183 @@ __global__ __launch_bounds__(W *(N / fft_e(N, EP))) void fresnel_cols(float2 *__
 #pragma unroll
       for (int i = 0; i < E; ++i) base[(size_t)(t + T * i) * nx] = v[i];
     }
+  }
+}
+
+// Persistent forms of the two passes: a grid sized to what the compute units
+// hold at once walks the work items (rows, or column strips of one frame) with a
+// grid stride and loads the next item's data into registers while it transforms
+// the current one, so memory latency overlaps the FFT.
+
+// Raw input of one row chunk (8 pixels per 16-byte load) held in registers.
+template <int IN>
+struct RowIn {
+  uint4 q;      // 8 uint16 (kInU16, kInU16MinusMean)
+  float4 a, b;  // 8 floats (kInF32) or the mean (kInU16MinusMean)
+};
+
+template <int N, int EP, int IN>
+__device__ __forceinline__ void row_load(RowIn<IN> (&in)[N / 8 / (N / fft_e(N, EP)) > 0 ? N / 8 / (N / fft_e(N, EP)) : 1],
+                                         const void *src, const float *mean, size_t base, size_t mbase, int t,
+                                         bool live) {
+  constexpr int T = N / fft_e(N, EP), L = N / 8 / T > 0 ? N / 8 / T : 1;
+#pragma unroll
+  for (int l = 0; l < L; ++l) {
+    const int c = t + T * l;
+    if (!live || c >= N / 8) continue;
+    if constexpr (IN == kInF32) {
+      const float4 *s4 = reinterpret_cast<const float4 *>(static_cast<const float *>(src) + base) + 2 * c;
+      in[l].a = s4[0];
+      in[l].b = s4[1];
+    } else {
+      in[l].q = reinterpret_cast<const uint4 *>(static_cast<const uint16_t *>(src) + base)[c];
+      if constexpr (IN == kInU16MinusMean) {
+        const float4 *m4 = reinterpret_cast<const float4 *>(mean + mbase) + 2 * c;
+        in[l].a = m4[0];
+        in[l].b = m4[1];
+      }
+    }
+  }
+}
+
+template <int N, int EP, int ROWS, int IN, bool SPLIT>
+__global__ __launch_bounds__(ROWS *(N / fft_e(N, EP))) void fresnel_rows_persist(
+    const void *__restrict__ src, const float *__restrict__ mean, int ny, int nframes,
+    const float2 *__restrict__ chirp_x, const float2 *__restrict__ chirp_y, const float2 *__restrict__ tw,
+    float2 *__restrict__ out) {
+  constexpr int E = FftCfg<N, EP>::E, T = FftCfg<N, EP>::T, L = N / 8 / T > 0 ? N / 8 / T : 1;
+  static_assert(FftCfg<N, EP>::P > 1 && N / 8 >= T, "persistent rows need an LDS exchange and 8 pixels per thread");
+  typedef typename std::conditional<SPLIT, float, float2>::type Slot;
+  __shared__ Slot lds[ROWS * FftCfg<N, EP>::LDSN];
+  const int t = threadIdx.x % T, r = threadIdx.x / T;
+  float *stage = reinterpret_cast<float *>(lds + r * FftCfg<N, EP>::LDSN);
+  const int groups = (ny + ROWS - 1) / ROWS, items = groups * nframes;
+  float2 cx[E];
+#pragma unroll
+  for (int i = 0; i < E; ++i) cx[i] = chirp_x[t + T * i];
+  auto where = [&](int item, int &row, size_t &base, size_t &mbase) {
+    const int f = item / groups;
+    row = (item - f * groups) * ROWS + r;
+    const bool live = row < ny;
+    base = ((size_t)f * ny + (live ? row : 0)) * N;
+    mbase = (size_t)(live ? row : 0) * N;
+    return live;
+  };
+  RowIn<IN> cur[L], nxt[L];
+  int item = blockIdx.x, row;
+  size_t base, mbase;
+  bool live = item < items && where(item, row, base, mbase);
+  if (item < items) row_load<N, EP, IN>(cur, src, mean, base, mbase, t, live);
+  for (; item < items; item += gridDim.x) {
+    const int item2 = item + gridDim.x;
+    int row2;
+    size_t base2 = 0, mbase2 = 0;
+    const bool live2 = item2 < items && where(item2, row2, base2, mbase2);
+    if (item2 < items) row_load<N, EP, IN>(nxt, src, mean, base2, mbase2, t, live2);
+#pragma unroll
+    for (int l = 0; l < L; ++l) {
+      const int c = t + T * l;
+      float x[8];
+      if constexpr (IN == kInF32) {
+        x[0] = cur[l].a.x; x[1] = cur[l].a.y; x[2] = cur[l].a.z; x[3] = cur[l].a.w;
+        x[4] = cur[l].b.x; x[5] = cur[l].b.y; x[6] = cur[l].b.z; x[7] = cur[l].b.w;
+      } else {
+        union {
+          uint4 q;
+          uint16_t h[8];
+        } u;
+        u.q = cur[l].q;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) x[e] = (float)u.h[e];
+        if constexpr (IN == kInU16MinusMean) {
+          x[0] -= cur[l].a.x; x[1] -= cur[l].a.y; x[2] -= cur[l].a.z; x[3] -= cur[l].a.w;
+          x[4] -= cur[l].b.x; x[5] -= cur[l].b.y; x[6] -= cur[l].b.z; x[7] -= cur[l].b.w;
+        }
+      }
+      if (!live) {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) x[e] = 0.0f;
+      }
+#pragma unroll
+      for (int e = 0; e < 8; ++e) stage[8 * c + e] = x[e];
+    }
+    __syncthreads();
+    const float2 cy = chirp_y[live ? row : 0];
+    float2 v[E];
+#pragma unroll
+    for (int i = 0; i < E; ++i) {
+      const float val = stage[t + T * i];
+      const float2 c = cmul(cx[i], cy);
+      v[i] = make_float2(val * c.x, val * c.y);
+    }
+    __syncthreads();
+    fft_passes<N, EP, 0, SPLIT>(v, t, tw, lds + r * FftCfg<N, EP>::LDSN, RowSlot{});
+    if (live) {
+#pragma unroll
+      for (int i = 0; i < E; ++i) out[base + t + T * i] = v[i];
+    }
+    __syncthreads();  // the LDS is reused by the next item
+#pragma unroll
+    for (int l = 0; l < L; ++l) cur[l] = nxt[l];
+    live = live2;
+    row = row2;
+    base = base2;
+  }
+}
+
+template <int N, int EP, int W, bool R16, bool SPLIT>
+__global__ __launch_bounds__(W *(N / fft_e(N, EP))) void fresnel_cols_persist(float2 *__restrict__ data, int nx,
+                                                                       int nframes, const float2 *__restrict__ tw,
+                                                                       h2 *__restrict__ r16, float scale) {
+  constexpr int E = FftCfg<N, EP>::E, T = FftCfg<N, EP>::T;
+  static_assert(FftCfg<N, EP>::P > 1, "persistent columns need an LDS exchange");
+  typedef typename std::conditional<SPLIT, float, float2>::type Slot;
+  __shared__ Slot lds[W * FftCfg<N, EP>::LDSN];
+  const int c = threadIdx.x % W, t = threadIdx.x / W;
+  const int strips = (nx + W - 1) / W, items = strips * nframes;
+  auto where = [&](int item, size_t &off) {
+    const int f = item / strips;
+    const int col = (item - f * strips) * W + c;
+    const bool live = col < nx;
+    off = (size_t)f * N * nx + (live ? col : 0);
+    return live;
+  };
+  float2 cur[E], nxt[E];
+  int item = blockIdx.x;
+  size_t off = 0;
+  bool live = item < items && where(item, off);
+  if (item < items) {
+#pragma unroll
+    for (int i = 0; i < E; ++i) cur[i] = live ? data[off + (size_t)(t + T * i) * nx] : make_float2(0.f, 0.f);
+  }
+  for (; item < items; item += gridDim.x) {
+    const int item2 = item + gridDim.x;
+    size_t off2 = 0;
+    const bool live2 = item2 < items && where(item2, off2);
+    if (item2 < items) {
+#pragma unroll
+      for (int i = 0; i < E; ++i) nxt[i] = live2 ? data[off2 + (size_t)(t + T * i) * nx] : make_float2(0.f, 0.f);
+    }
+    fft_passes<N, EP, 0, SPLIT>(cur, t, tw, lds, ColSlot<W>{c});
+    if (live) {
+      if constexpr (R16) {
+#pragma unroll
+        for (int i = 0; i < E; ++i) {
+          h2 q;
+          q.x = (_Float16)(cur[i].x * scale);
+          q.y = (_Float16)(cur[i].y * scale);
+          r16[off + (size_t)(t + T * i) * nx] = q;
+        }
+      } else {
+#pragma unroll
+        for (int i = 0; i < E; ++i) data[off + (size_t)(t + T * i) * nx] = cur[i];
+      }
+    }
+    __syncthreads();  // the LDS is reused by the next item
+#pragma unroll
+    for (int i = 0; i < E; ++i) cur[i] = nxt[i];
+    live = live2;
+    off = off2;
   }
 }
 
@@ -196,19 +376,37 @@ __global__ __launch_bounds__(256) void frame_mean(const uint16_t *__restrict__ f
 // sizes below kTunedMinN have only shape 0.
 constexpr int kTunedMinN = 512;
 
-template <int N, int EP, int R>
+template <int N, int EP, int R, bool SPLIT = false>
 hipError_t rows_launch(const Plan &pl, int in_mode, const void *src, const float *mean, int nframes, float2 *out,
                        hipStream_t s) {
   dim3 grid((pl.ny + R - 1) / R, nframes), block(R * FftCfg<N, EP>::T);
   if (in_mode == kInU16)
-    hipLaunchKernelGGL((fresnel_rows<N, EP, R, kInU16>), grid, block, 0, s, src, mean, pl.ny, pl.chirp_x,
+    hipLaunchKernelGGL((fresnel_rows<N, EP, R, kInU16, SPLIT>), grid, block, 0, s, src, mean, pl.ny, pl.chirp_x,
                        pl.chirp_y, pl.tw_x, out);
   else if (in_mode == kInU16MinusMean)
-    hipLaunchKernelGGL((fresnel_rows<N, EP, R, kInU16MinusMean>), grid, block, 0, s, src, mean, pl.ny, pl.chirp_x,
+    hipLaunchKernelGGL((fresnel_rows<N, EP, R, kInU16MinusMean, SPLIT>), grid, block, 0, s, src, mean, pl.ny, pl.chirp_x,
                        pl.chirp_y, pl.tw_x, out);
   else
-    hipLaunchKernelGGL((fresnel_rows<N, EP, R, kInF32>), grid, block, 0, s, src, mean, pl.ny, pl.chirp_x,
+    hipLaunchKernelGGL((fresnel_rows<N, EP, R, kInF32, SPLIT>), grid, block, 0, s, src, mean, pl.ny, pl.chirp_x,
                        pl.chirp_y, pl.tw_x, out);
+  return hipGetLastError();
+}
+
+template <int N, int EP, int R, bool SPLIT = false>
+hipError_t rows_persist_launch(const Plan &pl, int in_mode, const void *src, const float *mean, int nframes,
+                               float2 *out, hipStream_t s) {
+  const int items = (pl.ny + R - 1) / R * nframes;
+  const int grid = items < 8 * pl.cus ? items : 8 * pl.cus;  // one-wave groups: eight per compute unit
+  dim3 g(grid), block(R * FftCfg<N, EP>::T);
+  if (in_mode == kInU16)
+    hipLaunchKernelGGL((fresnel_rows_persist<N, EP, R, kInU16, SPLIT>), g, block, 0, s, src, mean, pl.ny, nframes,
+                       pl.chirp_x, pl.chirp_y, pl.tw_x, out);
+  else if (in_mode == kInU16MinusMean)
+    hipLaunchKernelGGL((fresnel_rows_persist<N, EP, R, kInU16MinusMean, SPLIT>), g, block, 0, s, src, mean, pl.ny,
+                       nframes, pl.chirp_x, pl.chirp_y, pl.tw_x, out);
+  else
+    hipLaunchKernelGGL((fresnel_rows_persist<N, EP, R, kInF32, SPLIT>), g, block, 0, s, src, mean, pl.ny, nframes,
+                       pl.chirp_x, pl.chirp_y, pl.tw_x, out);
   return hipGetLastError();
 }
 
@@ -217,20 +415,38 @@ hipError_t rows_n(const Plan &pl, int shape, int in_mode, const void *src, const
                   float2 *out, hipStream_t s) {
   ProfScope ps("fresnel_rows", s);
   if constexpr (N >= kTunedMinN) {
+    if (shape == 6) return rows_persist_launch<N, 16, 1>(pl, in_mode, src, mean, nframes, out, s);
+    if (shape == 7) return rows_persist_launch<N, 32, 2>(pl, in_mode, src, mean, nframes, out, s);
     if (shape == 1) return rows_launch<N, 32, rows_per_wg<N, 32>()>(pl, in_mode, src, mean, nframes, out, s);
     if (shape == 2) return rows_launch<N, 32, 2>(pl, in_mode, src, mean, nframes, out, s);
     if (shape == 3) return rows_launch<N, 16, 1>(pl, in_mode, src, mean, nframes, out, s);
+    if (shape == 4) return rows_launch<N, 32, 2, true>(pl, in_mode, src, mean, nframes, out, s);
+    if (shape == 5) return rows_launch<N, 16, rows_per_wg<N, 16>(), true>(pl, in_mode, src, mean, nframes, out, s);
   }
   return rows_launch<N, 16, rows_per_wg<N, 16>()>(pl, in_mode, src, mean, nframes, out, s);
 }
 
-template <int N, int EP, int W>
+template <int N, int EP, int W, bool SPLIT = false>
 hipError_t cols_launch(const Plan &pl, int nframes, float2 *data, h2 *r16, float scale, hipStream_t s) {
   dim3 grid((pl.nx + W - 1) / W, nframes), block(W * FftCfg<N, EP>::T);
   if (r16)
-    hipLaunchKernelGGL((fresnel_cols<N, EP, W, true>), grid, block, 0, s, data, pl.nx, pl.tw_y, r16, scale);
+    hipLaunchKernelGGL((fresnel_cols<N, EP, W, true, SPLIT>), grid, block, 0, s, data, pl.nx, pl.tw_y, r16, scale);
   else
-    hipLaunchKernelGGL((fresnel_cols<N, EP, W, false>), grid, block, 0, s, data, pl.nx, pl.tw_y, r16, scale);
+    hipLaunchKernelGGL((fresnel_cols<N, EP, W, false, SPLIT>), grid, block, 0, s, data, pl.nx, pl.tw_y, r16, scale);
+  return hipGetLastError();
+}
+
+template <int N, int EP, int W, bool SPLIT = false>
+hipError_t cols_persist_launch(const Plan &pl, int nframes, float2 *data, h2 *r16, float scale, hipStream_t s) {
+  const int items = (pl.nx + W - 1) / W * nframes;
+  const int grid = items < pl.cus ? items : pl.cus;  // one resident group per compute unit (LDS, registers)
+  dim3 g(grid), block(W * FftCfg<N, EP>::T);
+  if (r16)
+    hipLaunchKernelGGL((fresnel_cols_persist<N, EP, W, true, SPLIT>), g, block, 0, s, data, pl.nx, nframes, pl.tw_y,
+                       r16, scale);
+  else
+    hipLaunchKernelGGL((fresnel_cols_persist<N, EP, W, false, SPLIT>), g, block, 0, s, data, pl.nx, nframes, pl.tw_y,
+                       r16, scale);
   return hipGetLastError();
 }
 
@@ -238,9 +454,13 @@ template <int N>
 hipError_t cols_n(const Plan &pl, int shape, int nframes, float2 *data, h2 *r16, float scale, hipStream_t s) {
   ProfScope ps(r16 ? "fresnel_cols_r16" : "fresnel_cols", s);
   if constexpr (N >= kTunedMinN) {
+    if (shape == 5) return cols_persist_launch<N, 16, cols_per_wg<N, 16>()>(pl, nframes, data, r16, scale, s);
+    if (shape == 6) return cols_persist_launch<N, 16, cols_per_wg<N, 16>(), true>(pl, nframes, data, r16, scale, s);
     constexpr int Wh = cols_per_wg<N, 16>() / 2 > 0 ? cols_per_wg<N, 16>() / 2 : 1;
     if (shape == 1) return cols_launch<N, 16, Wh>(pl, nframes, data, r16, scale, s);
     if (shape == 2) return cols_launch<N, 32, cols_per_wg<N, 32>()>(pl, nframes, data, r16, scale, s);
+    if (shape == 3) return cols_launch<N, 16, cols_per_wg<N, 16>(), true>(pl, nframes, data, r16, scale, s);
+    if (shape == 4) return cols_launch<N, 32, cols_per_wg<N, 32>(), true>(pl, nframes, data, r16, scale, s);
   }
   return cols_launch<N, 16, cols_per_wg<N, 16>()>(pl, nframes, data, r16, scale, s);
 }
@@ -315,7 +535,9 @@ hipError_t launch_fresnel_r16(const Plan &pl, const Tune &tu, const uint16_t *fr
   hipError_t e = hipGetLastError();
   if (e == hipSuccess) e = rows_dispatch(pl, tu.rows, kInF32, mean, nullptr, 1, m, s);
   if (e == hipSuccess) e = cols_dispatch(pl, tu.cols, 1, m, nullptr, 0.f, s);
-  const int group = fresnel_group_frames(pl.nx, pl.ny, nframes, tu.group);
+  // the group buffer holds the default group: larger tuned groups are clamped to it
+  const int dflt = fresnel_group_frames(pl.nx, pl.ny, nframes, 0);
+  const int group = fresnel_group_frames(pl.nx, pl.ny, nframes, tu.group < dflt ? tu.group : dflt);
   for (int f0 = 0; f0 < nframes && e == hipSuccess; f0 += group) {
     const int n = nframes - f0 < group ? nframes - f0 : group;
     const size_t off = (size_t)f0 * npix;

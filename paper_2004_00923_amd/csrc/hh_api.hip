@@ -136,6 +136,8 @@ const Plan *get_plan(const hh_params &p) {
   pl.device = dev;
   pl.nx = p.nx;
   pl.ny = p.ny;
+  int cus = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0) pl.cus = cus;
   if ((e = upload(&pl.chirp_x, chirp_table(p.nx, alpha))) != hipSuccess ||
       (e = upload(&pl.chirp_y, chirp_table(p.ny, alpha))) != hipSuccess ||
       (e = upload(&pl.tw_x, twiddle_table(p.nx))) != hipSuccess ||
@@ -265,13 +267,13 @@ void put_tune(const hh_params &p, const Tune &t) {
 int default_group(const hh_params &p) { return fresnel_group_frames(p.nx, p.ny, 1 << 30, 0); }
 
 hh_status check_tune(const hh_params &p, const hh_tuning &t) {
-  const int nrows = p.nx >= 512 ? 4 : 1, ncols = p.ny >= 512 ? 3 : 1;
+  const int nrows = p.nx >= 512 ? 8 : 1, ncols = p.ny >= 512 ? 7 : 1;
   if (t.fft_rows < 0 || t.fft_rows >= nrows) return fail(HH_E_INVALID, "fft_rows=%d: %d shape(s) at nx=%d", t.fft_rows, nrows, p.nx);
   if (t.fft_cols < 0 || t.fft_cols >= ncols) return fail(HH_E_INVALID, "fft_cols=%d: %d shape(s) at ny=%d", t.fft_cols, ncols, p.ny);
   if (t.gram_pxw != 256 && t.gram_pxw != 512 && t.gram_pxw != 1024)
     return fail(HH_E_INVALID, "gram_pxw=%d: must be 256, 512 or 1024", t.gram_pxw);
-  if (t.group < 0 || t.group > default_group(p))
-    return fail(HH_E_INVALID, "group=%d: must be in [0, %d] (0 = default)", t.group, default_group(p));
+  if (t.group < 0 || t.group > 4 * default_group(p))
+    return fail(HH_E_INVALID, "group=%d: must be in [0, %d] (0 = default)", t.group, 4 * default_group(p));
   return HH_OK;
 }
 
@@ -779,9 +781,9 @@ hh_status hh_autotune(const hh_params *p, const uint16_t *frames, void *workspac
   // coordinate descent: row shape, column shape, group size, split-K chunk
   const int dg = default_group(*p);
   std::vector<std::pair<int Tune::*, std::vector<int>>> axes = {
-      {&Tune::rows, p->nx >= 512 ? std::vector<int>{0, 1, 2, 3} : std::vector<int>{0}},
-      {&Tune::cols, p->ny >= 512 ? std::vector<int>{0, 1, 2} : std::vector<int>{0}},
-      {&Tune::group, {0, std::max(1, dg / 2), std::max(1, dg / 4)}},
+      {&Tune::rows, p->nx >= 512 ? std::vector<int>{0, 1, 2, 3, 4, 5, 6, 7} : std::vector<int>{0}},
+      {&Tune::cols, p->ny >= 512 ? std::vector<int>{0, 1, 2, 3, 4, 5, 6} : std::vector<int>{0}},
+      {&Tune::group, {0, std::max(1, dg / 2), std::max(1, dg / 4), std::min(2 * dg, p->nt), std::min(4 * dg, p->nt)}},
       {&Tune::pxw, {256, 512, 1024}}};
   for (auto &ax : axes) {
     for (int val : ax.second) {

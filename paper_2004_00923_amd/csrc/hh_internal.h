@@ -19,6 +19,7 @@ struct Plan {
   float2 *chirp_y = nullptr;  // [ny]  exp(-i alpha (n - ny/2)^2)
   float2 *tw_x = nullptr;     // [nx]  exp(-2 pi i j / nx)
   float2 *tw_y = nullptr;     // [ny]  exp(-2 pi i j / ny)
+  int cus = 256;              // compute units of the device (sizes persistent grids)
 };
 
 // Returns nullptr and sets the error text on failure.
