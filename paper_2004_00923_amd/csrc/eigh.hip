@@ -181,10 +181,44 @@ __global__ __launch_bounds__(kThreads) void eigh_jacobi(EighBatch batch, int max
     }
   }
 
+  // C into A (unscaled): from the covariance partials when given (the same
+  // fixed-order sums as the covariance's own assembly), else from cov.  The
+  // lower triangle and the real diagonal are read; A is Hermitian.
+  if (pr.part2) {
+    const int D = pr.D, G2 = pr.g2;
+    const size_t L = partial_len(D);
+    double2 *Cw = reinterpret_cast<double2 *>(const_cast<double *>(pr.cov));
+    for (int e = tid; e < n * n; e += kThreads) {
+      const int s = e / n, t = e - (e / n) * n;
+      const int lo = s < t ? s : t, hi = s < t ? t : s;
+      double re = 0.0, qst = 0.0, qts = 0.0, mm = 0.0, alo = 0.0, ahi = 0.0, ais = 0.0, ait = 0.0;
+      for (int g = 0; g < G2; ++g) {
+        const double *q = pr.part2 + g * L;
+        re += q[lo * D + hi];
+        qst += q[(size_t)D * D + s * D + t];
+        qts += q[(size_t)D * D + t * D + s];
+        alo += q[2 * D * D + lo];
+        ahi += q[2 * D * D + hi];
+        ais += q[2 * D * D + D + s];
+        ait += q[2 * D * D + D + t];
+        mm += q[2 * D * D + 2 * D];
+      }
+      const double2 c = make_double2((re + mm) + (alo + ahi), (qst - qts) + (ait - ais));
+      Cw[e] = c;
+      A[s * LD + t] = c;
+    }
+  } else {
+    for (int e = tid; e < n * n; e += kThreads) {
+      const int i = e / n, j = e - (e / n) * n;
+      A[i * LD + j] = C[e];
+    }
+  }
+  __syncthreads();
   // Frobenius norm -> exact power-of-two scale
   double s2 = 0.0;
   for (int e = tid; e < n * n; e += kThreads) {
-    const double2 v = C[e];
+    const int i = e / n, j = e - (e / n) * n;
+    const double2 v = i > j ? A[i * LD + j] : i < j ? zconj(A[j * LD + i]) : make_double2(A[i * LD + i].x, 0.0);
     s2 += v.x * v.x + v.y * v.y;
   }
   red[tid] = s2;
@@ -199,14 +233,18 @@ __global__ __launch_bounds__(kThreads) void eigh_jacobi(EighBatch batch, int max
   const double scale = fro > 0.0 ? ldexp(1.0, -ilogb(fro)) : 1.0;
   const double abs2 = (kAbsTol * fro * scale) * (kAbsTol * fro * scale);
 
-  // Hermitian input: the lower triangle and the real diagonal are read.
+  // Hermitian input: the lower triangle and the real diagonal are read.  Each
+  // thread reads the two mirrored entries of its own pair (i > j), so the
+  // in-place update needs no extra barrier.
   for (int e = tid; e < n * n; e += kThreads) {
     const int i = e / n, j = e - (e / n) * n;
-    double2 a;
-    if (i > j) a = C[i * n + j];
-    else if (i < j) a = zconj(C[j * n + i]);
-    else a = make_double2(C[i * n + i].x, 0.0);
-    A[i * LD + j] = zscale(a, scale);
+    if (i > j) {
+      const double2 a = zscale(A[i * LD + j], scale);
+      A[i * LD + j] = a;
+      A[j * LD + i] = zconj(a);
+    } else if (i == j) {
+      A[i * LD + i] = make_double2(A[i * LD + i].x * scale, 0.0);
+    }
     V[i * LD + j] = make_double2(i == j ? 1.0 : 0.0, 0.0);
   }
   __syncthreads();

@@ -29,8 +29,6 @@ typedef double v4d __attribute__((ext_vector_type(4)));
 // Output of accumulator register r on lane l of a 32x32 MFMA block.
 __device__ __forceinline__ int acc_row(int lane, int r) { return 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3); }
 
-// Length (doubles) of one workgroup partial: S, Q (D x D each), a (re, im), m^H m, pad.
-__host__ __device__ constexpr int partial_len(int D) { return 2 * D * D + 2 * D + 2; }
 // second-level partial count (the first level is summed in this many segments)
 constexpr int kGroups2 = 16;
 
@@ -806,11 +804,12 @@ GramLayout gram_layout(int nt, long long npix, int pxw) {
 }
 
 namespace {
-hipError_t gram_tail(const GramLayout &L, int nt, double *partial, double *partial2, double *cov, hipStream_t s);
+hipError_t gram_tail(const GramLayout &L, int nt, double *partial, double *partial2, double *cov, hipStream_t s,
+                     bool finalize);
 }
 
 hipError_t launch_gram(const GramLayout &L, const float2 *holo, int nt, long long npix, double *partial,
-                       double *partial2, double *cov, hipStream_t s, int precision) {
+                       double *partial2, double *cov, hipStream_t s, int precision, bool finalize) {
   if (precision != HH_FP32 && nt <= 32) {
     ProfScope ps("gram_partial_lp", s);
     const dim3 g(L.groups), b(256);
@@ -832,22 +831,22 @@ hipError_t launch_gram(const GramLayout &L, const float2 *holo, int nt, long lon
   }
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  return gram_tail(L, nt, partial, partial2, cov, s);
+  return gram_tail(L, nt, partial, partial2, cov, s, finalize);
 }
 
 hipError_t launch_gram_r16(const GramLayout &L, const h2 *r16, const float2 *m, int nt, long long npix, float inv_s,
-                           double *partial, double *partial2, double *cov, hipStream_t s) {
+                           double *partial, double *partial2, double *cov, hipStream_t s, bool finalize) {
   {
     ProfScope ps("gram_partial_r16", s);
     hipLaunchKernelGGL(gram_partial_r16, dim3(L.groups), dim3(256), 0, s, r16, m, nt, npix, L.pxw, inv_s, partial);
   }
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  return gram_tail(L, nt, partial, partial2, cov, s);
+  return gram_tail(L, nt, partial, partial2, cov, s, finalize);
 }
 
 hipError_t launch_gram_u16(const GramLayout &L, const uint16_t *frames, int nt, long long npix, double *partial,
-                           double *partial2, double *cov, hipStream_t s) {
+                           double *partial2, double *cov, hipStream_t s, bool finalize) {
   {
     ProfScope ps("gram_partial_u16", s);
     const dim3 g(L.groups), b(256);
@@ -859,12 +858,13 @@ hipError_t launch_gram_u16(const GramLayout &L, const uint16_t *frames, int nt, 
   }
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  return gram_tail(L, nt, partial, partial2, cov, s);
+  return gram_tail(L, nt, partial, partial2, cov, s, finalize);
 }
 
 namespace {
 // fixed-order reduction of the workgroup partials and Hermitian assembly
-hipError_t gram_tail(const GramLayout &L, int nt, double *partial, double *partial2, double *cov, hipStream_t s) {
+hipError_t gram_tail(const GramLayout &L, int nt, double *partial, double *partial2, double *cov, hipStream_t s,
+                     bool finalize) {
   hipError_t e;
   const int Lw = partial_len(L.D);
   {
@@ -873,7 +873,7 @@ hipError_t gram_tail(const GramLayout &L, int nt, double *partial, double *parti
                        L.groups2, partial2);
   }
   e = hipGetLastError();
-  if (e != hipSuccess) return e;
+  if (e != hipSuccess || !finalize) return e;
   {
     ProfScope ps("gram_finalize", s);
     hipLaunchKernelGGL(gram_finalize, dim3((nt * nt + 255) / 256), dim3(256), 0, s, partial2, L.groups2, L.D, nt,

@@ -326,6 +326,8 @@ struct StackViews {
   const float2 *m = nullptr;
   float inv_s = 1.f;
   double *cov = nullptr;
+  const double *part2 = nullptr;  // covariance partials the eigensolver assembles into cov
+  int g2 = 0, D = 0;
 };
 
 hipError_t enqueue_front(const hh_params &p, const Plan *pl, const PipeLayout &L, char *ws, const uint16_t *frames,
@@ -335,6 +337,9 @@ hipError_t enqueue_front(const hh_params &p, const Plan *pl, const PipeLayout &L
   const GramLayout gl = gram_layout(p.nt, npix, tu.pxw);  // offsets in L are sized for the smallest chunk
   double *part = reinterpret_cast<double *>(ws + L.part), *part2 = reinterpret_cast<double *>(ws + L.part2);
   v.cov = reinterpret_cast<double *>(ws + L.cov);
+  v.part2 = part2;
+  v.g2 = gl.groups2;
+  v.D = gl.D;
   if (L.r16) {
     h2 *r = reinterpret_cast<h2 *>(ws + L.r16buf);
     float2 *m = reinterpret_cast<float2 *>(ws + L.m);
@@ -344,18 +349,18 @@ hipError_t enqueue_front(const hh_params &p, const Plan *pl, const PipeLayout &L
     hipError_t e = launch_fresnel_r16(*pl, tu, frames, p.nt, reinterpret_cast<float *>(ws + L.mean), m,
                                       reinterpret_cast<float2 *>(ws + L.group), r, 1.0f / v.inv_s, s);
     if (e != hipSuccess) return e;
-    return launch_gram_r16(gl, r, m, p.nt, npix, v.inv_s, part, part2, v.cov, s);
+    return launch_gram_r16(gl, r, m, p.nt, npix, v.inv_s, part, part2, v.cov, s, false);
   }
   if (frames) {
     float2 *H = reinterpret_cast<float2 *>(ws + L.holo);
     hipError_t e = launch_fresnel(*pl, tu, frames, p.nt, H, s);
     if (e != hipSuccess) return e;
     v.H = H;
-    if (p.precision == HH_EXACT) return launch_gram_u16(gl, frames, p.nt, npix, part, part2, v.cov, s);
+    if (p.precision == HH_EXACT) return launch_gram_u16(gl, frames, p.nt, npix, part, part2, v.cov, s, false);
   } else {
     v.H = holo;
   }
-  return launch_gram(gl, v.H, p.nt, npix, part, part2, v.cov, s, p.precision);
+  return launch_gram(gl, v.H, p.nt, npix, part, part2, v.cov, s, p.precision, false);
 }
 
 hipError_t enqueue_back(const hh_params &p, const StackViews &v, const double *V, float *image, hipStream_t s) {
@@ -419,10 +424,14 @@ hh_status run_batch(const hh_params *p, int n, const BatchItem *it, void *worksp
   for (int i = 0; i < n && e == hipSuccess; ++i) {
     const PipeLayout L = pipe_layout(p + i, with_holo);
     e = enqueue_front(p[i], plans[i], L, ws, it[i].frames, it[i].holo, views[i], s);
-    probs[i] = EighProblem{p[i].nt, views[i].cov,
+    probs[i] = EighProblem{p[i].nt,
+                           views[i].cov,
                            it[i].evals ? it[i].evals : reinterpret_cast<double *>(ws + L.evals),
                            it[i].evecs ? it[i].evecs : reinterpret_cast<double *>(ws + L.evecs),
-                           it[i].info ? it[i].info : reinterpret_cast<int *>(ws + L.info)};
+                           it[i].info ? it[i].info : reinterpret_cast<int *>(ws + L.info),
+                           views[i].part2,
+                           views[i].g2,
+                           views[i].D};
     ws += align_up(L.total);
   }
   if (e == hipSuccess) e = launch_eigh_batch(probs.data(), n, 40, s);
@@ -601,7 +610,10 @@ hh_status hh_pipeline(const hh_params *p, const uint16_t *frames, float *image, 
   hipStream_t s = (hipStream_t)stream;
   StackViews v;
   hipError_t e = enqueue_front(*p, pl, L, ws, frames, nullptr, v, s);
-  if (e == hipSuccess) e = launch_eigh(p->nt, v.cov, ev, V, inf, 40, s);
+  if (e == hipSuccess) {
+    const EighProblem prob{p->nt, v.cov, ev, V, inf, v.part2, v.g2, v.D};
+    e = launch_eigh_batch(&prob, 1, 40, s);
+  }
   if (e == hipSuccess) e = enqueue_back(*p, v, V, image, s);
   if (e != hipSuccess) return device_fail(e, "hh_pipeline");
   return HH_OK;

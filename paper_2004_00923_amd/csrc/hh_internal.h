@@ -53,6 +53,11 @@ hipError_t launch_fresnel_r16(const Plan &pl, const Tune &tu, const uint16_t *fr
                               float2 *m, float2 *group_buf, h2 *r16, float scale, hipStream_t s);
 
 // Step (b): split-K Gram partials, fixed-order reduction, Hermitian assembly.
+// Length (doubles) of one covariance partial: S, Q (D x D each), a (re, im), m^H m, pad.
+// C[s][t] = S[min][max] + m^H m + a[s] + a[t] + i (Q[s][t] - Q[t][s] + a'[t] - a'[s]),
+// a = re part, a' = im part of the rank-one vector.
+__host__ __device__ constexpr int partial_len(int D) { return 2 * D * D + 2 * D + 2; }
+
 struct GramLayout {
   int nb = 1;              // 32-frame blocks (1 or 2)
   int D = 32;              // 32 * nb
@@ -73,22 +78,29 @@ constexpr int kGramPxwMin = 256;  // the workspace is sized for the smallest spl
 GramLayout gram_layout(int nt, long long npix, int pxw = kGramPxwMin);
 // precision: HH_FP32, or a low-precision form of the R^H R contraction (n_t <= 32;
 // larger stacks use the FP32 form).
+// finalize = false: stop after the second-level partials (the eigensolver assembles C).
 hipError_t launch_gram(const GramLayout &L, const float2 *holo, int nt, long long npix,
-                       double *partial, double *partial2, double *cov, hipStream_t s, int precision = HH_FP32);
+                       double *partial, double *partial2, double *cov, hipStream_t s, int precision = HH_FP32,
+                       bool finalize = true);
 // Exact covariance from the frames, C = N_pix I^T I (n_t <= 64; frames 16-byte aligned).
 hipError_t launch_gram_u16(const GramLayout &L, const uint16_t *frames, int nt, long long npix, double *partial,
-                           double *partial2, double *cov, hipStream_t s);
+                           double *partial2, double *cov, hipStream_t s, bool finalize = true);
 // FP16 storage form: H = m 1^T + r16 / s with inv_s = 1 / s (n_t <= 32).
 hipError_t launch_gram_r16(const GramLayout &L, const h2 *r16, const float2 *m, int nt, long long npix, float inv_s,
-                           double *partial, double *partial2, double *cov, hipStream_t s);
+                           double *partial, double *partial2, double *cov, hipStream_t s, bool finalize = true);
 
 // Step (c): one workgroup per problem; problems are passed by value (kernel argument).
+// One eigenproblem.  Either cov holds C (complex128 [n][n]), or part2 holds the
+// covariance's second-level partial sums (g2 partials of the D-wide layout), in
+// which case the solver assembles C itself and also stores it to cov.
 struct EighProblem {
   int n;
   const double *cov;
   double *evals;
   double *evecs;
   int *info;
+  const double *part2 = nullptr;
+  int g2 = 0, D = 0;
 };
 constexpr int kMaxEighBatch = 64;
 struct EighBatch {
