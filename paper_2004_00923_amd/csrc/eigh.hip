@@ -14,7 +14,7 @@
 // of A it owns, in place (the four outputs share the four inputs); barrier;
 // (2) wave 0 computes the next round's rotations from three entries each, with
 // hardware reciprocal / reciprocal-square-root seeds refined by Newton steps,
-// while waves 1-3 rotate V's (row, pair) entries in place; barrier.  C is scaled
+// while the other waves rotate V's (row, pair) entries in place; barrier.  C is scaled
 // by an exact power of two so that its Frobenius norm is O(1).
 // A rotation is skipped when |beta| <= 1e-15 sqrt(|a b|) or |beta| <= 1e-18 ||C||_F;
 // the iteration stops when every off-diagonal entry passes that test.  The result
@@ -26,7 +26,10 @@ namespace {
 
 constexpr double kRelTol = 1e-15;
 constexpr double kAbsTol = 1e-18;
-constexpr int kThreads = 256;
+// threads per problem: 256 for n <= 32 (rounds are latency-bound), 1024 for n <= 64
+// (a round has four times the 2x2 blocks and V items, so it is throughput-bound)
+template <int NMAX>
+constexpr int threads_for() { return NMAX <= 32 ? 256 : 1024; }
 constexpr size_t kCuLdsBytes = 160 * 1024;
 
 __device__ __forceinline__ double2 zmul(double2 a, double2 b) {
@@ -138,7 +141,8 @@ __device__ __forceinline__ double2 rotated_entry(const double2 *A, int ld, const
 }
 
 template <int NMAX>
-__global__ __launch_bounds__(kThreads) void eigh_jacobi(EighBatch batch, int max_sweeps) {
+__global__ __launch_bounds__(threads_for<NMAX>()) void eigh_jacobi(EighBatch batch, int max_sweeps) {
+  constexpr int kThreads = threads_for<NMAX>();
   // one workgroup per problem of the batch
   const EighProblem &pr = batch.prob[blockIdx.x];
   const int n = pr.n;
@@ -150,7 +154,7 @@ __global__ __launch_bounds__(kThreads) void eigh_jacobi(EighBatch batch, int max
   constexpr int NPMAX = NMAX / 2;
   constexpr int NBLK = NPMAX * (NPMAX + 1) / 2;
   constexpr int BPT = (NBLK + kThreads - 1) / kThreads;          // A blocks per thread
-  constexpr int VTH = kThreads - 64;                              // threads rotating V (waves 1..3)
+  constexpr int VTH = kThreads - 64;                              // threads rotating V (waves 1..)
   constexpr int VPT = (NMAX * NPMAX + VTH - 1) / VTH;             // V (row, pair) items per thread
   extern __shared__ double2 smem[];
   double2 *const A = smem;              // [n][LD]
@@ -404,7 +408,7 @@ __global__ __launch_bounds__(kThreads) void eigh_jacobi(EighBatch batch, int max
 
 template <int NMAX>
 constexpr size_t eigh_static_lds() {
-  return 2 * sizeof(RoundParams<NMAX>) + sizeof(int) + kThreads * sizeof(double) + NMAX * sizeof(int) + 512;
+  return 2 * sizeof(RoundParams<NMAX>) + sizeof(int) + threads_for<NMAX>() * sizeof(double) + NMAX * sizeof(int) + 512;
 }
 
 template <int NMAX>
@@ -423,7 +427,7 @@ hipError_t launch_batch(const EighBatch &b, int count, int max_sweeps, hipStream
     if (dev >= 0 && dev < 64) attr_set[dev] = true;
   }
   ProfScope ps("eigh_jacobi", s);
-  hipLaunchKernelGGL((eigh_jacobi<NMAX>), dim3(count), dim3(kThreads), shmem, s, b, max_sweeps);
+  hipLaunchKernelGGL((eigh_jacobi<NMAX>), dim3(count), dim3(threads_for<NMAX>()), shmem, s, b, max_sweeps);
   return hipGetLastError();
 }
 

@@ -233,6 +233,9 @@ class Server:
         `source`: pinned host uint16 tensor [n_src][ny][nx] of frames replayed cyclically."""
         if tuple(source.shape[1:]) != (spec.ny, spec.nx):
             raise ValueError(f"camera {spec.name}: source frames must be [n][{spec.ny}][{spec.nx}]")
+        if spec.precision in ("fp16store", "exact"):
+            raise ValueError(f"camera {spec.name}: the rings hold FP32 holograms; form {spec.precision} "
+                             "starts from frames and does not apply")
         ring = RingPlan(spec.window, spec.hop)
         need = self.adm.request(spec, ring)
         self.cams.append(_Camera(spec, ring, source, self.adm.image_buffers, self.device))
