@@ -152,6 +152,9 @@ def main():
                     help="stacks per step, processed by one hh_pipeline_batch call (1 = hh_pipeline)")
     ap.add_argument("--precision", default="fp32",
                     help="arithmetic of the covariance contraction: fp32, bf16, fp16, bf16x3, fp16x3, fp8e4m3")
+    ap.add_argument("--streams", type=int, default=4,
+                    help="consecutive batches alternate over this many streams, each with its own workspace "
+                         "and images (one batch's latency-bound eigensolver overlaps the next batch's FFTs)")
     ap.add_argument("--autotune", action="store_true",
                     help="run the autotuner first (untimed) instead of the pinned launch choices")
     ap.add_argument("--tuning", default=None,
@@ -206,20 +209,32 @@ def main():
     tuning_str = ",".join(str(tuning[k]) for k in ("fft_rows", "fft_cols", "gram_pxw", "group"))
     img1 = torch.empty((NY, NX), dtype=torch.float32, device=dev)
     info = torch.empty(1, dtype=torch.int32, device=dev)
+    S = max(1, args.streams) if B > 1 else 1
+    streams = [torch.cuda.current_stream(dev)] + [torch.cuda.Stream(device=dev) for _ in range(S - 1)]
     if B > 1:
         ps = [p] * B
-        bimgs = [torch.empty((NY, NX), dtype=torch.float32, device=dev) for _ in range(B)]
-        binfo = [torch.empty(1, dtype=torch.int32, device=dev) for _ in range(B)]
-        bws = hh.alloc_workspace(hh.batch_workspace_bytes(ps), dev)
+        # one workspace, image set and stream per lane of the double buffering
+        lanes = []
+        for _ in range(S):
+            imgs_l = [torch.empty((NY, NX), dtype=torch.float32, device=dev) for _ in range(B)]
+            info_l = [torch.empty(1, dtype=torch.int32, device=dev) for _ in range(B)]
+            lanes.append((imgs_l, info_l, hh.alloc_workspace(hh.batch_workspace_bytes(ps), dev)))
+        binfo = lanes[0][1]
         # stack j of step i reads input (i + j) % 4: consecutive stacks never share an input
-        batches = [hh.Batch(ps, [frames[(r + j) % 4] for j in range(B)], bimgs, bws, infos=binfo)
-                   for r in range(4)]
+        batches = [[hh.Batch(ps, [frames[(r + j) % 4] for j in range(B)], imgs_l, ws_l, infos=info_l)
+                    for r in range(4)] for imgs_l, info_l, ws_l in lanes]
+        if S > 1:
+            main = streams[0]
+            for st in streams[1:]:
+                st.wait_stream(main)
 
-    def step(i, single=False):
+    def step(i, single=False, one_stream=False):
         if single or B == 1:
             hh.hh_pipeline(p, frames[i % 4], img1, ws1, info=info)
+        elif one_stream:
+            batches[0][i % 4].run(streams[0])
         else:
-            batches[i % 4].run()
+            batches[i % S][i % 4].run(streams[i % S])
 
     print(f"bench: warmup {args.warmup}", file=sys.stderr, flush=True)
     for i in range(args.warmup):
@@ -239,13 +254,13 @@ def main():
     value = NT * B * args.steps / elapsed
 
     # per-kernel durations from HIP events recorded around each launch, over a
-    # second timed pass of the same K steps
+    # second timed pass of the same K steps on one stream (kernels in isolation)
     hh.profile_reset()
     hh.profile_enable(True)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     for i in range(args.steps):
-        step(i)
+        step(i, one_stream=True)
     torch.cuda.synchronize()
     prof_elapsed = time.perf_counter() - t1
     hh.profile_enable(False)
@@ -300,7 +315,8 @@ def main():
         "config": {"workload": "one 32x1024x1024 uint16 stack per step (4 seeded stacks rotated), "
                                f"lambda 785 nm, pitch 20 um, z 0.3 m, PCs 2..31, {args.precision}",
                    "stacks_per_s": value / NT, "precision": args.precision, "jacobi_sweeps": sweeps,
-                   "stacks_per_step": B, "ms_per_stack": ms_per_step / B, "tuning": tuning},
+                   "stacks_per_step": B, "ms_per_stack": ms_per_step / B, "tuning": tuning,
+                   "streams": S},
         "roofline": roofline,
         "stack_roofline": {"bytes_per_stack": sb,
                            "achieved": sb * B / (ms_per_step * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,

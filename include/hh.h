@@ -53,6 +53,13 @@ enum {
   HH_E_NOT_CONVERGED = 5  /* reserved for host-side reporting of info < 0 */
 };
 
+/* Eigensolver of step (c) used by the pipeline entry points (both FP64, both give
+ * the eigenpairs of Eq. (5) to rounding; they differ in speed and in what info counts). */
+enum {
+  HH_EIGH_JACOBI = 0,   /* parallel cyclic Jacobi (hh_eigh) */
+  HH_EIGH_TRIDIAG = 1   /* Householder reduction to real tridiagonal form, implicit QL (hh_eigh_tridiag) */
+};
+
 /* Arithmetic of the covariance contraction of step (b), Eq. (4), and of the
  * hologram storage.  In every form the stack is split per pixel as
  * H = m 1^T + R (m a per-pixel reference, the temporal mean) and the rank-one
@@ -102,7 +109,8 @@ typedef struct {
                            The paper's 1-based ascending n1..n2 maps to nt-n2..nt-n1. */
   int32_t precision;    /* HH_FP32 ... HH_EXACT (covariance contraction, hologram storage) */
   int32_t proj_mode;    /* HH_PROJ_AUTO / _DIRECT / _COMPLEMENT */
-  int32_t reserved;     /* must be 0 */
+  int32_t eigh_solver;  /* HH_EIGH_JACOBI (0) or HH_EIGH_TRIDIAG (1): the step (c) solver of the
+                           pipeline entry points */
 } hh_params;
 
 /* Bytes of device workspace hh_pipeline needs for *p (0 if *p is invalid). */
@@ -171,6 +179,16 @@ hh_status hh_eigh_ex(int32_t nt, const double *cov, double *evals, double *evecs
                      int32_t *info, int32_t max_sweeps, void *stream);
 
 /*
+ * Step (c) as hh_eigh, by Householder reduction of C to a real tridiagonal matrix
+ * (reflectors whose phases make the off-diagonal real) followed by implicit QL
+ * with shifts, in FP64, one workgroup per problem; the eigenvector phases and the
+ * order are fixed as in hh_eigh.  info : number of QL iterations (>= 0), or -1 if
+ * some eigenvalue needed more than max_iter (>= 0; the pipelines use 40).
+ */
+hh_status hh_eigh_tridiag(int32_t nt, const double *cov, double *evals, double *evecs,
+                          int32_t *info, int32_t max_iter, void *stream);
+
+/*
  * Steps (d)+(e), Eqs. (6)-(7): the power image of the kept components, with the
  * projection fused into the |.|^2 sum (the components are never stored).
  *   holo  : complex64 [nt][ny][nx].
@@ -216,7 +234,7 @@ typedef struct {
   float *image;           /* float32 [ny][nx] output */
   double *evals;          /* float64 [nt] output, or NULL */
   double *evecs;          /* complex128 [nt][nt] output, or NULL */
-  int32_t *info;          /* int32 [1] output (Jacobi sweeps, -1 = not converged), or NULL */
+  int32_t *info;          /* int32 [1] output (solver iterations, -1 = not converged), or NULL */
 } hh_stack;
 
 /* Bytes of workspace hh_pipeline_batch needs for the n stacks described by p[0..n-1]
@@ -243,7 +261,7 @@ typedef struct {
   float *image;           /* float32 [ny][nx] output */
   double *evals;          /* float64 [nt] output, or NULL */
   double *evecs;          /* complex128 [nt][nt] output, or NULL */
-  int32_t *info;          /* int32 [1] output (Jacobi sweeps, -1 = not converged), or NULL */
+  int32_t *info;          /* int32 [1] output (solver iterations, -1 = not converged), or NULL */
 } hh_window;
 
 /* Bytes of workspace hh_analyze_batch needs for the n stacks described by p[0..n-1]

@@ -140,54 +140,16 @@ __device__ __forceinline__ double2 rotated_entry(const double2 *A, int ld, const
   return x;
 }
 
-template <int NMAX>
-__global__ __launch_bounds__(threads_for<NMAX>()) void eigh_jacobi(EighBatch batch, int max_sweeps) {
-  constexpr int kThreads = threads_for<NMAX>();
-  // one workgroup per problem of the batch
-  const EighProblem &pr = batch.prob[blockIdx.x];
-  const int n = pr.n;
-  const double2 *__restrict__ C = reinterpret_cast<const double2 *>(pr.cov);
-  double *__restrict__ evals = pr.evals;
-  double2 *__restrict__ evecs = reinterpret_cast<double2 *>(pr.evecs);
-  int *__restrict__ info = pr.info;
+// C into A (scaled by an exact power of two so that its Frobenius norm is O(1))
+// and V = I, both [n][NMAX + 1] in LDS.  C comes from the covariance partials when
+// given (the same fixed-order sums as the covariance's own assembly), else from
+// cov; the lower triangle and the real diagonal are read, A is Hermitian.
+// Returns the scale; red[0] holds ||C||_F * scale on return.
+template <int NMAX, int kThreads>
+__device__ double load_scaled(const EighProblem &pr, double2 *A, double2 *V, double *red) {
   constexpr int LD = NMAX + 1;
-  constexpr int NPMAX = NMAX / 2;
-  constexpr int NBLK = NPMAX * (NPMAX + 1) / 2;
-  constexpr int BPT = (NBLK + kThreads - 1) / kThreads;          // A blocks per thread
-  constexpr int VTH = kThreads - 64;                              // threads rotating V (waves 1..)
-  constexpr int VPT = (NMAX * NPMAX + VTH - 1) / VTH;             // V (row, pair) items per thread
-  extern __shared__ double2 smem[];
-  double2 *const A = smem;              // [n][LD]
-  double2 *const V = smem + NMAX * LD;  // [n][LD]
-  __shared__ RoundParams<NMAX> prm[2];
-  __shared__ int flag;
-  __shared__ double red[kThreads];
-  __shared__ int rank_of[NMAX];
-  const int tid = threadIdx.x;
-  const int m = n + (n & 1);
-  const int np = m / 2;
-  const int nblk = np * (np + 1) / 2;
-
-  // blocks (P <= Q) owned by this thread, unranked once
-  int bP[BPT], bQ[BPT];
-#pragma unroll
-  for (int u = 0; u < BPT; ++u) {
-    int b = tid + kThreads * u, P = 0;
-    bP[u] = -1;
-    bQ[u] = -1;
-    if (b < nblk) {
-      while (b >= np - P) {
-        b -= np - P;
-        ++P;
-      }
-      bP[u] = P;
-      bQ[u] = P + b;
-    }
-  }
-
-  // C into A (unscaled): from the covariance partials when given (the same
-  // fixed-order sums as the covariance's own assembly), else from cov.  The
-  // lower triangle and the real diagonal are read; A is Hermitian.
+  const int n = pr.n, tid = threadIdx.x;
+  const double2 *__restrict__ C = reinterpret_cast<const double2 *>(pr.cov);
   if (pr.part2) {
     const int D = pr.D, G2 = pr.g2;
     const size_t L = partial_len(D);
@@ -235,7 +197,6 @@ __global__ __launch_bounds__(threads_for<NMAX>()) void eigh_jacobi(EighBatch bat
   __syncthreads();
   const double fro = sqrt(red[0]);
   const double scale = fro > 0.0 ? ldexp(1.0, -ilogb(fro)) : 1.0;
-  const double abs2 = (kAbsTol * fro * scale) * (kAbsTol * fro * scale);
 
   // Hermitian input: the lower triangle and the real diagonal are read.  Each
   // thread reads the two mirrored entries of its own pair (i > j), so the
@@ -251,6 +212,100 @@ __global__ __launch_bounds__(threads_for<NMAX>()) void eigh_jacobi(EighBatch bat
     }
     V[i * LD + j] = make_double2(i == j ? 1.0 : 0.0, 0.0);
   }
+  __syncthreads();
+  if (tid == 0) red[0] = fro * scale;
+  __syncthreads();
+  return scale;
+}
+
+// Sorts by decreasing eigenvalue (ties: lower index first) from A's diagonal and V's
+// columns, undoes the scale, fixes each column's phase (the lowest row whose modulus
+// is within 1e-12 of the largest becomes real > 0) and writes the outputs.
+template <int NMAX>
+__device__ void store_sorted(const EighProblem &pr, const double2 *A, const double2 *V, double scale, int *rank_of,
+                             int info_value) {
+  constexpr int LD = NMAX + 1;
+  const int n = pr.n, tid = threadIdx.x;
+  double *__restrict__ evals = pr.evals;
+  double2 *__restrict__ evecs = reinterpret_cast<double2 *>(pr.evecs);
+  if (tid < n) {
+    const double di = A[tid * LD + tid].x;
+    int rk = 0;
+    for (int j = 0; j < n; ++j) {
+      const double dj = A[j * LD + j].x;
+      rk += (dj > di) || (dj == di && j < tid);
+    }
+    rank_of[tid] = rk;
+    evals[rk] = di / scale;
+  }
+  __syncthreads();
+  if (tid < n) {
+    const int k = tid, col = rank_of[k];
+    double mx = 0.0;
+    for (int j = 0; j < n; ++j) {
+      const double2 v = V[j * LD + k];
+      mx = fmax(mx, sqrt(v.x * v.x + v.y * v.y));
+    }
+    int js = 0;
+    for (int j = n - 1; j >= 0; --j) {
+      const double2 v = V[j * LD + k];
+      if (sqrt(v.x * v.x + v.y * v.y) >= mx * (1.0 - 1e-12)) js = j;
+    }
+    const double2 vs = V[js * LD + k];
+    const double ms = sqrt(vs.x * vs.x + vs.y * vs.y);
+    const double2 ph = ms > 0.0 ? make_double2(vs.x / ms, -vs.y / ms) : make_double2(1.0, 0.0);
+    for (int j = 0; j < n; ++j) {
+      const double2 v = (j == js) ? make_double2(ms, 0.0) : zmul(V[j * LD + k], ph);
+      evecs[j * n + col] = v;
+    }
+  }
+  if (tid == 0) *pr.info = info_value;
+}
+
+template <int NMAX>
+__global__ __launch_bounds__(threads_for<NMAX>()) void eigh_jacobi(EighBatch batch, int max_sweeps) {
+  constexpr int kThreads = threads_for<NMAX>();
+  // one workgroup per problem of the batch
+  const EighProblem &pr = batch.prob[blockIdx.x];
+  const int n = pr.n;
+  constexpr int LD = NMAX + 1;
+  constexpr int NPMAX = NMAX / 2;
+  constexpr int NBLK = NPMAX * (NPMAX + 1) / 2;
+  constexpr int BPT = (NBLK + kThreads - 1) / kThreads;          // A blocks per thread
+  constexpr int VTH = kThreads - 64;                              // threads rotating V (waves 1..)
+  constexpr int VPT = (NMAX * NPMAX + VTH - 1) / VTH;             // V (row, pair) items per thread
+  extern __shared__ double2 smem[];
+  double2 *const A = smem;              // [n][LD]
+  double2 *const V = smem + NMAX * LD;  // [n][LD]
+  __shared__ RoundParams<NMAX> prm[2];
+  __shared__ int flag;
+  __shared__ double red[kThreads];
+  __shared__ int rank_of[NMAX];
+  const int tid = threadIdx.x;
+  const int m = n + (n & 1);
+  const int np = m / 2;
+  const int nblk = np * (np + 1) / 2;
+
+  // blocks (P <= Q) owned by this thread, unranked once
+  int bP[BPT], bQ[BPT];
+#pragma unroll
+  for (int u = 0; u < BPT; ++u) {
+    int b = tid + kThreads * u, P = 0;
+    bP[u] = -1;
+    bQ[u] = -1;
+    if (b < nblk) {
+      while (b >= np - P) {
+        b -= np - P;
+        ++P;
+      }
+      bP[u] = P;
+      bQ[u] = P + b;
+    }
+  }
+
+  const double scale = load_scaled<NMAX, kThreads>(pr, A, V, red);
+  const double fro = red[0] / scale;  // Frobenius norm of C (exactly, scale is a power of two)
+  const double abs2 = (kAbsTol * fro * scale) * (kAbsTol * fro * scale);
   __syncthreads();
 
   int sweeps = 0;
@@ -370,40 +425,231 @@ __global__ __launch_bounds__(threads_for<NMAX>()) void eigh_jacobi(EighBatch bat
     }
   }
 
-  // sort by decreasing eigenvalue (ties: lower index first), undo the scale
-  if (tid < n) {
-    const double di = A[tid * LD + tid].x;
-    int rk = 0;
-    for (int j = 0; j < n; ++j) {
-      const double dj = A[j * LD + j].x;
-      rk += (dj > di) || (dj == di && j < tid);
+  store_sorted<NMAX>(pr, A, V, scale, rank_of, converged ? sweeps : -1);
+}
+
+
+// ---------------------------------------------------------------------------
+// Step (c) by Householder reduction to real tridiagonal form and implicit QL,
+// FP64, one workgroup of 256 threads per problem (n <= 64).
+//  1. For k = 0 .. n-3 the reflector H_k = I - 2 u u^H (u unit, supported on
+//     rows k+1 ..) maps column k below the diagonal to alpha_k e_1, |alpha_k| =
+//     its norm, with the phase chosen opposite to its first entry (no
+//     cancellation).  The trailing block B becomes B - u w^H - w u^H,
+//     w = 2 (p - (u^H p) u), p = B u.  u_k is kept in column k of A.
+//  2. V = H_0 H_1 ... H_{n-3} (applied right to left to the identity), then the
+//     diagonal unitary D with delta_{k+1} = delta_k alpha_k / |alpha_k| makes the
+//     off-diagonals real and non-negative: A = (V D) T (V D)^H.
+//  3. Implicit QL with Wilkinson-type shifts on the real tridiagonal T (wave 0:
+//     every lane runs the same scalar recurrence, lane r applies each plane
+//     rotation to row r of V D).
+// info = the number of QL iterations, or -1 if one eigenvalue needed more than
+// max_iter of them.
+template <int NMAX>
+__global__ __launch_bounds__(256) void eigh_tridiag(EighBatch batch, int max_iter) {
+  constexpr int kThreads = 256, LD = NMAX + 1, G = kThreads / 64;
+  const EighProblem &pr = batch.prob[blockIdx.x];
+  const int n = pr.n;
+  extern __shared__ double2 smem[];
+  double2 *const A = smem;              // [n][LD]
+  double2 *const V = smem + NMAX * LD;  // [n][LD]
+  __shared__ double2 part[G][64];
+  __shared__ double2 wv[64];
+  __shared__ double2 alpha[NMAX];
+  __shared__ double dg[NMAX], od[NMAX];
+  __shared__ double red[kThreads];
+  __shared__ int rank_of[NMAX];
+  const int tid = threadIdx.x, lane = tid & 63, grp = tid >> 6;
+
+  const double scale = load_scaled<NMAX, kThreads>(pr, A, V, red);
+
+  // 1. Householder reduction
+  for (int k = 0; k + 2 < n; ++k) {
+    const int m = n - k - 1;
+    if (tid < 64) {
+      const double2 x = lane < m ? A[(k + 1 + lane) * LD + k] : make_double2(0.0, 0.0);
+      double s2 = x.x * x.x + x.y * x.y;
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) s2 += __shfl_xor(s2, o);
+      const double x0r = __shfl(x.x, 0), x0i = __shfl(x.y, 0);
+      const double ax0 = sqrt(x0r * x0r + x0i * x0i);
+      const double an = sqrt(s2);
+      double2 u = make_double2(0.0, 0.0), al = make_double2(0.0, 0.0);
+      if (an > 0.0) {
+        const double phr = ax0 > 0.0 ? x0r / ax0 : 1.0, phi = ax0 > 0.0 ? x0i / ax0 : 0.0;
+        al = make_double2(-phr * an, -phi * an);
+        const double inv = 1.0 / sqrt(2.0 * an * (an + ax0));
+        const double2 v = lane == 0 ? make_double2(x.x - al.x, x.y - al.y) : x;
+        u = make_double2(v.x * inv, v.y * inv);
+      }
+      if (lane < m) A[(k + 1 + lane) * LD + k] = u;
+      if (lane == 0) alpha[k] = al;
     }
-    rank_of[tid] = rk;
-    evals[rk] = di / scale;
+    __syncthreads();
+    // p = B u: group g sums the columns j = g, g + G, ... of row `lane`
+    if (lane < m) {
+      double2 acc = make_double2(0.0, 0.0);
+      const double2 *row = A + (k + 1 + lane) * LD + (k + 1);
+      for (int j = grp; j < m; j += G) acc = zadd(acc, zmul(row[j], A[(k + 1 + j) * LD + k]));
+      part[grp][lane] = acc;
+    }
+    __syncthreads();
+    if (tid < 64) {
+      double2 p = make_double2(0.0, 0.0);
+      const double2 u = lane < m ? A[(k + 1 + lane) * LD + k] : make_double2(0.0, 0.0);
+      if (lane < m) {
+#pragma unroll
+        for (int g = 0; g < G; ++g) p = zadd(p, part[g][lane]);
+      }
+      double kk = u.x * p.x + u.y * p.y;  // Re(conj(u) p)
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) kk += __shfl_xor(kk, o);
+      if (lane < m) wv[lane] = make_double2(2.0 * (p.x - kk * u.x), 2.0 * (p.y - kk * u.y));
+    }
+    __syncthreads();
+    // B <- B - u w^H - w u^H
+    for (int e = tid; e < m * m; e += kThreads) {
+      const int i = e / m, j = e - (e / m) * m;
+      const double2 ui = A[(k + 1 + i) * LD + k], uj = A[(k + 1 + j) * LD + k];
+      const double2 wi = wv[i], wj = wv[j];
+      double2 &b = A[(k + 1 + i) * LD + (k + 1 + j)];
+      b = zsub(b, zadd(zmul(ui, zconj(wj)), zmul(wi, zconj(uj))));
+    }
+    __syncthreads();
+  }
+
+  // 2. V = H_0 ... H_{n-3} from the right end, then the phases
+  for (int k = n - 3; k >= 0; --k) {
+    const int m = n - k - 1;
+    // s_c = sum_i conj(u_i) V[k+1+i][c] for the columns c = k+1 .. n-1
+    if (lane < m) {
+      double2 acc = make_double2(0.0, 0.0);
+      for (int i = grp; i < m; i += G) acc = zadd(acc, zmul(zconj(A[(k + 1 + i) * LD + k]), V[(k + 1 + i) * LD + (k + 1 + lane)]));
+      part[grp][lane] = acc;
+    }
+    __syncthreads();
+    if (tid < 64 && lane < m) {
+      double2 sc = make_double2(0.0, 0.0);
+#pragma unroll
+      for (int g = 0; g < G; ++g) sc = zadd(sc, part[g][lane]);
+      wv[lane] = sc;
+    }
+    __syncthreads();
+    for (int e = tid; e < m * m; e += kThreads) {
+      const int i = e / m, c = e - (e / m) * m;
+      const double2 ui = A[(k + 1 + i) * LD + k];
+      double2 &v = V[(k + 1 + i) * LD + (k + 1 + c)];
+      const double2 t = zmul(ui, wv[c]);
+      v = make_double2(v.x - 2.0 * t.x, v.y - 2.0 * t.y);
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    // real tridiagonal: diagonal, off-diagonal |alpha_k|; the phases delta_k go to wv
+    for (int i = 0; i < n; ++i) dg[i] = A[i * LD + i].x;
+    double2 dl = make_double2(1.0, 0.0);
+    wv[0] = dl;
+    for (int k = 0; k + 1 < n; ++k) {
+      const double2 a = k + 2 < n ? alpha[k] : A[(k + 1) * LD + k];
+      const double aa = sqrt(a.x * a.x + a.y * a.y);
+      od[k] = aa;
+      if (aa > 0.0) dl = zmul(dl, make_double2(a.x / aa, a.y / aa));
+      wv[k + 1] = dl;
+    }
+    od[n - 1] = 0.0;
   }
   __syncthreads();
-  // phase fix: the lowest row whose modulus is within 1e-12 of the largest becomes real > 0
-  if (tid < n) {
-    const int k = tid, col = rank_of[k];
-    double mx = 0.0;
-    for (int j = 0; j < n; ++j) {
-      const double2 v = V[j * LD + k];
-      mx = fmax(mx, sqrt(v.x * v.x + v.y * v.y));
-    }
-    int js = 0;
-    for (int j = n - 1; j >= 0; --j) {
-      const double2 v = V[j * LD + k];
-      if (sqrt(v.x * v.x + v.y * v.y) >= mx * (1.0 - 1e-12)) js = j;
-    }
-    const double2 vs = V[js * LD + k];
-    const double ms = sqrt(vs.x * vs.x + vs.y * vs.y);
-    const double2 ph = ms > 0.0 ? make_double2(vs.x / ms, -vs.y / ms) : make_double2(1.0, 0.0);
-    for (int j = 0; j < n; ++j) {
-      const double2 v = (j == js) ? make_double2(ms, 0.0) : zmul(V[j * LD + k], ph);
-      evecs[j * n + col] = v;
-    }
+  for (int e = tid; e < n * n; e += kThreads) {
+    const int i = e / n, j = e - (e / n) * n;
+    V[i * LD + j] = zmul(V[i * LD + j], wv[j]);
   }
-  if (tid == 0) *info = converged ? sweeps : -1;
+  __syncthreads();
+
+  // 3. implicit QL on (dg, od), wave 0.  Lane j keeps d_j and e_j in registers; the
+  // scalar recurrence (identical on every lane) reads them with readlane and writes
+  // them back with a lane select.  A sweep's plane rotations are kept in LDS and
+  // then applied to the rows of V D (lane r, row r) with the running column held in
+  // registers.
+  if (tid < 64) {
+    const double eps = 2.220446049250313e-16;
+    double dL = lane < n ? dg[lane] : 0.0, eL = lane < n ? od[lane] : 0.0;
+    auto rd = [](double x, int j) {  // x of lane j (j wave-uniform)
+      return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(x), j),
+                              __builtin_amdgcn_readlane(__double2loint(x), j));
+    };
+    int total = 0;
+    bool ok = true;
+    for (int l = 0; l < n && ok; ++l) {
+      int iter = 0;
+      for (;;) {
+        int m = l;
+        while (m + 1 < n && fabs(rd(eL, m)) > eps * (fabs(rd(dL, m)) + fabs(rd(dL, m + 1)))) ++m;
+        if (m == l) break;
+        if (iter == max_iter) {
+          ok = false;
+          break;
+        }
+        ++iter;
+        ++total;
+        const double el = rd(eL, l), dl = rd(dL, l);
+        double g = (rd(dL, l + 1) - dl) / (2.0 * el);
+        double r = sqrt(g * g + 1.0);
+        g = rd(dL, m) - dl + el / (g + (g >= 0.0 ? r : -r));
+        double sn = 1.0, cs = 1.0, p = 0.0;
+        int last = l;  // lowest rotated index + 1 .. m: columns last .. m change
+        bool split = false;
+        for (int i = m - 1; i >= l; --i) {
+          const double ei = rd(eL, i);
+          const double f = sn * ei, b = cs * ei;
+          const double r2 = f * f + g * g;
+          if (r2 == 0.0) {  // the matrix split at i: restart on the reduced problem
+            const double di1 = rd(dL, i + 1) - p;
+            if (lane == i + 1) { dL = di1; eL = 0.0; }
+            if (lane == m) eL = 0.0;
+            last = i + 1;
+            split = true;
+            break;
+          }
+          const double ir = rsq64(r2);
+          r = r2 * ir;
+          if (lane == i + 1) eL = r;
+          sn = f * ir;
+          cs = g * ir;
+          const double di = rd(dL, i);
+          g = rd(dL, i + 1) - p;
+          r = (di - g) * sn + 2.0 * cs * b;
+          p = sn * r;
+          if (lane == i + 1) dL = g + p;
+          g = cs * r - b;
+          if (lane == 0) {
+            wv[i] = make_double2(cs, sn);
+          }
+          last = i;
+        }
+        // the rotations i = m-1 .. last, in that order, on the rows of V
+        if (lane < n && last < m) {
+          double2 hi = V[lane * LD + m];
+          for (int i = m - 1; i >= last; --i) {
+            const double2 q = wv[i];  // (c, s)
+            const double2 lo = V[lane * LD + i];
+            V[lane * LD + i + 1] = make_double2(q.y * lo.x + q.x * hi.x, q.y * lo.y + q.x * hi.y);
+            hi = make_double2(q.x * lo.x - q.y * hi.x, q.x * lo.y - q.y * hi.y);
+          }
+          V[lane * LD + last] = hi;
+        }
+        if (split) continue;
+        if (lane == l) { dL -= p; eL = g; }
+        if (lane == m) eL = 0.0;
+      }
+    }
+    if (lane < n) dg[lane] = dL;
+    if (lane == 0) red[0] = ok ? (double)total : -1.0;
+  }
+  __syncthreads();
+  const int info_value = (int)red[0];
+  for (int i = tid; i < n; i += kThreads) A[i * LD + i] = make_double2(dg[i], 0.0);
+  __syncthreads();
+  store_sorted<NMAX>(pr, A, V, scale, rank_of, info_value);
 }
 
 template <int NMAX>
@@ -431,24 +677,52 @@ hipError_t launch_batch(const EighBatch &b, int count, int max_sweeps, hipStream
   return hipGetLastError();
 }
 
+template <int NMAX>
+hipError_t launch_tridiag(const EighBatch &b, int count, int max_iter, hipStream_t s) {
+  static bool attr_set[64] = {};
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  const size_t shmem = 2 * (size_t)NMAX * (NMAX + 1) * sizeof(double2);  // A and V
+  if (dev < 0 || dev >= 64 || !attr_set[dev]) {
+    e = hipFuncSetAttribute((const void *)eigh_tridiag<NMAX>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)shmem);
+    if (e != hipSuccess) return e;
+    if (dev >= 0 && dev < 64) attr_set[dev] = true;
+  }
+  ProfScope ps("eigh_tridiag", s);
+  hipLaunchKernelGGL((eigh_tridiag<NMAX>), dim3(count), dim3(256), shmem, s, b, max_iter);
+  return hipGetLastError();
+}
+
 }  // namespace
 
-hipError_t launch_eigh_batch(const EighProblem *probs, int count, int max_sweeps, hipStream_t s) {
-  // problems with n <= 32 and n > 32 go to the two kernel sizes, kMaxEighBatch per launch
-  for (int big = 0; big < 2; ++big) {
-    EighBatch b{};
-    int m = 0;
-    for (int i = 0; i < count; ++i) {
-      if ((probs[i].n > 32) != (big == 1)) continue;
-      b.prob[m++] = probs[i];
-      if (m == kMaxEighBatch) {
-        hipError_t e = big ? launch_batch<64>(b, m, max_sweeps, s) : launch_batch<32>(b, m, max_sweeps, s);
-        if (e != hipSuccess) return e;
+hipError_t launch_eigh_batch(const EighProblem *probs, int count, int max_iter, hipStream_t s) {
+  // problems go to the kernel of their method and size class (n <= 32, n <= 64),
+  // at most kMaxEighBatch per launch
+  for (int method : {HH_EIGH_JACOBI, HH_EIGH_TRIDIAG}) {
+    for (int big = 0; big < 2; ++big) {
+      EighBatch b{};
+      int m = 0;
+      auto flush = [&]() -> hipError_t {
+        hipError_t e = hipSuccess;
+        if (m == 0) return e;
+        if (method == HH_EIGH_JACOBI)
+          e = big ? launch_batch<64>(b, m, max_iter, s) : launch_batch<32>(b, m, max_iter, s);
+        else
+          e = big ? launch_tridiag<64>(b, m, max_iter, s) : launch_tridiag<32>(b, m, max_iter, s);
         m = 0;
+        return e;
+      };
+      for (int i = 0; i < count; ++i) {
+        if ((probs[i].n > 32) != (big == 1) || probs[i].method != method) continue;
+        b.prob[m++] = probs[i];
+        if (m == kMaxEighBatch) {
+          const hipError_t e = flush();
+          if (e != hipSuccess) return e;
+        }
       }
-    }
-    if (m > 0) {
-      hipError_t e = big ? launch_batch<64>(b, m, max_sweeps, s) : launch_batch<32>(b, m, max_sweeps, s);
+      const hipError_t e = flush();
       if (e != hipSuccess) return e;
     }
   }
@@ -458,6 +732,7 @@ hipError_t launch_eigh_batch(const EighProblem *probs, int count, int max_sweeps
 hipError_t launch_eigh(int nt, const double *cov, double *evals, double *evecs, int *info, int max_sweeps,
                        hipStream_t s) {
   EighProblem p{nt, cov, evals, evecs, info};
+  p.method = HH_EIGH_JACOBI;
   return launch_eigh_batch(&p, 1, max_sweeps, s);
 }
 

@@ -194,7 +194,8 @@ hh_status check_shape(const hh_params *p) {
   if (p->nx <= 0 || p->ny <= 0) return fail(HH_E_INVALID, "nx, ny must be > 0");
   if (!is_pow2(p->nx) || !is_pow2(p->ny) || p->nx < 8 || p->ny < 8 || p->nx > 4096 || p->ny > 4096)
     return fail(HH_E_UNSUPPORTED, "nx=%d ny=%d: frame sides must be powers of two in [8, 4096]", p->nx, p->ny);
-  if (p->reserved != 0) return fail(HH_E_INVALID, "reserved field must be 0");
+  if (p->eigh_solver != HH_EIGH_TRIDIAG && p->eigh_solver != HH_EIGH_JACOBI)
+    return fail(HH_E_INVALID, "eigh_solver=%d unknown", p->eigh_solver);
   return HH_OK;
 }
 
@@ -431,7 +432,8 @@ hh_status run_batch(const hh_params *p, int n, const BatchItem *it, void *worksp
                            it[i].info ? it[i].info : reinterpret_cast<int *>(ws + L.info),
                            views[i].part2,
                            views[i].g2,
-                           views[i].D};
+                           views[i].D,
+                           p[i].eigh_solver};
     ws += align_up(L.total);
   }
   if (e == hipSuccess) e = launch_eigh_batch(probs.data(), n, 40, s);
@@ -544,6 +546,20 @@ hh_status hh_eigh_ex(int32_t nt, const double *cov, double *evals, double *evecs
   return HH_OK;
 }
 
+hh_status hh_eigh_tridiag(int32_t nt, const double *cov, double *evals, double *evecs, int32_t *info,
+                          int32_t max_iter, void *stream) {
+  if (nt < 2 || nt > 64) return fail(HH_E_UNSUPPORTED, "nt=%d: must be in [2, 64]", nt);
+  if (!cov || !evals || !evecs || !info) return fail(HH_E_INVALID, "cov, evals, evecs, info must be non-NULL");
+  if (!aligned(cov, 16) || !aligned(evecs, 16) || !aligned(evals, 8) || !aligned(info, 4))
+    return fail(HH_E_INVALID, "eigh arrays misaligned");
+  if (max_iter < 0) return fail(HH_E_INVALID, "max_iter must be >= 0");
+  EighProblem prob{nt, cov, evals, evecs, info};
+  prob.method = HH_EIGH_TRIDIAG;
+  hipError_t e = launch_eigh_batch(&prob, 1, max_iter, (hipStream_t)stream);
+  if (e != hipSuccess) return device_fail(e, "hh_eigh_tridiag");
+  return HH_OK;
+}
+
 hh_status hh_eigh(int32_t nt, const double *cov, double *evals, double *evecs, int32_t *info, void *stream) {
   return hh_eigh_ex(nt, cov, evals, evecs, info, 40, stream);
 }
@@ -611,7 +627,7 @@ hh_status hh_pipeline(const hh_params *p, const uint16_t *frames, float *image, 
   StackViews v;
   hipError_t e = enqueue_front(*p, pl, L, ws, frames, nullptr, v, s);
   if (e == hipSuccess) {
-    const EighProblem prob{p->nt, v.cov, ev, V, inf, v.part2, v.g2, v.D};
+    const EighProblem prob{p->nt, v.cov, ev, V, inf, v.part2, v.g2, v.D, p->eigh_solver};
     e = launch_eigh_batch(&prob, 1, 40, s);
   }
   if (e == hipSuccess) e = enqueue_back(*p, v, V, image, s);

@@ -101,6 +101,7 @@ struct EighProblem {
   int *info;
   const double *part2 = nullptr;
   int g2 = 0, D = 0;
+  int method = HH_EIGH_JACOBI;  // HH_EIGH_JACOBI or HH_EIGH_TRIDIAG
 };
 constexpr int kMaxEighBatch = 64;
 struct EighBatch {
@@ -108,7 +109,8 @@ struct EighBatch {
 };
 hipError_t launch_eigh(int nt, const double *cov, double *evals, double *evecs, int *info,
                        int max_sweeps, hipStream_t s);
-hipError_t launch_eigh_batch(const EighProblem *probs, int count, int max_sweeps, hipStream_t s);
+// max_iter: Jacobi sweeps, or QL iterations per eigenvalue
+hipError_t launch_eigh_batch(const EighProblem *probs, int count, int max_iter, hipStream_t s);
 
 // Steps (d)+(e)
 hipError_t launch_project(const float2 *holo, int nt, long long npix, const double *V, int k_lo,

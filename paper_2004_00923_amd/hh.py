@@ -35,7 +35,7 @@ class hh_params(ctypes.Structure):
         ("k_hi", ctypes.c_int32),
         ("precision", ctypes.c_int32),
         ("proj_mode", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("eigh_solver", ctypes.c_int32),
     ]
 
 
@@ -52,10 +52,11 @@ class Params:
     pitch_m: float = 20e-6
     precision: int = HH_FP32
     proj_mode: int = HH_PROJ_AUTO
+    eigh_solver: int = 0          # HH_EIGH_JACOBI; 1 = HH_EIGH_TRIDIAG
 
     def c(self) -> hh_params:
         return hh_params(self.wavelength_m, self.distance_m, self.pitch_m, self.nx, self.ny, self.nt,
-                         self.k_lo, self.k_hi, self.precision, self.proj_mode, 0)
+                         self.k_lo, self.k_hi, self.precision, self.proj_mode, self.eigh_solver)
 
 
 class hh_stack(ctypes.Structure):
@@ -94,6 +95,7 @@ SIGNATURES = {
     "hh_covariance_frames": (ctypes.c_int32, [ctypes.POINTER(hh_params), _P, _P, _P, ctypes.c_size_t, _P]),
     "hh_eigh": (ctypes.c_int32, [ctypes.c_int32, _P, _P, _P, _P, _P]),
     "hh_eigh_ex": (ctypes.c_int32, [ctypes.c_int32, _P, _P, _P, _P, ctypes.c_int32, _P]),
+    "hh_eigh_tridiag": (ctypes.c_int32, [ctypes.c_int32, _P, _P, _P, _P, ctypes.c_int32, _P]),
     "hh_project_render": (ctypes.c_int32, [ctypes.POINTER(hh_params), _P, _P, _P, _P]),
     "hh_pipeline": (ctypes.c_int32, [ctypes.POINTER(hh_params), _P, _P, _P, _P, _P, _P, ctypes.c_size_t, _P]),
     "hh_fourier_render": (ctypes.c_int32, [ctypes.POINTER(hh_params), _P, _P, _P]),
@@ -217,6 +219,17 @@ def hh_eigh(nt: int, cov, evals, evecs, info, max_sweeps=None, stream=None):
         st = lib().hh_eigh_ex(nt, _ptr(cov), _ptr(evals), _ptr(evecs), _ptr(info), int(max_sweeps),
                               _stream(stream))
     _check(st)
+
+
+def hh_eigh_tridiag(nt: int, cov, evals, evecs, info, max_iter=40, stream=None):
+    """Step (c) by Householder tridiagonalisation and implicit QL; see include/hh.h."""
+    import torch
+    _dev_tensor(cov, torch.complex128, (nt, nt), "cov")
+    _dev_tensor(evals, torch.float64, (nt,), "evals")
+    _dev_tensor(evecs, torch.complex128, (nt, nt), "evecs")
+    _dev_tensor(info, torch.int32, (1,), "info")
+    _check(lib().hh_eigh_tridiag(nt, _ptr(cov), _ptr(evals), _ptr(evecs), _ptr(info), int(max_iter),
+                                 _stream(stream)))
 
 
 def hh_project_render(p: Params, holo, evecs, image, stream=None):

@@ -46,7 +46,7 @@ def good():
 @pytest.mark.parametrize("field,value,status", [
     ("nx", 1000, hh.HH_E_UNSUPPORTED), ("ny", 4, hh.HH_E_UNSUPPORTED), ("nx", 8192, hh.HH_E_UNSUPPORTED),
     ("nx", 0, hh.HH_E_INVALID), ("wavelength_m", 0.0, hh.HH_E_INVALID), ("wavelength_m", float("nan"), hh.HH_E_INVALID),
-    ("distance_m", 0.0, hh.HH_E_INVALID), ("pitch_m", -1.0, hh.HH_E_INVALID), ("reserved", 1, hh.HH_E_INVALID),
+    ("distance_m", 0.0, hh.HH_E_INVALID), ("pitch_m", -1.0, hh.HH_E_INVALID), ("eigh_solver", 2, hh.HH_E_INVALID),
 ])
 def test_fresnel_rejects_bad_params(field, value, status):
     p = good()

@@ -80,23 +80,27 @@ def test_covariance_parity(hh, nt, ny, nx):
     assert np.all(np.diag(C).imag == 0)
 
 
+@pytest.mark.parametrize("solver", ["jacobi", "tridiag"])
 @pytest.mark.parametrize("n", [2, 3, 5, 8, 16, 31, 32, 33, 48, 64])
-def test_eigh_parity_random(hh, n):
+def test_eigh_parity_random(hh, n, solver):
     import torch
-    say(f"eigh n={n}")
+    say(f"eigh n={n} {solver}")
     rng = np.random.default_rng(n)
     X = rng.standard_normal((n, n + 3)) + 1j * rng.standard_normal((n, n + 3))
     C = X @ X.conj().T
-    _eigh_check(hh, C)
+    _eigh_check(hh, C, solver=solver)
 
 
-def _eigh_check(hh, C, sweeps_min=0):
+def _eigh_check(hh, C, sweeps_min=0, solver="jacobi"):
     import torch
     n = C.shape[0]
     ev = torch.empty(n, dtype=torch.float64, device="cuda")
     V = torch.empty((n, n), dtype=torch.complex128, device="cuda")
     info = torch.empty(1, dtype=torch.int32, device="cuda")
-    hh.hh_eigh(n, to_dev(C), ev, V, info)
+    if solver == "jacobi":
+        hh.hh_eigh(n, to_dev(C), ev, V, info)
+    else:
+        hh.hh_eigh_tridiag(n, to_dev(C), ev, V, info)
     w, Vg, inf = to_np(ev), to_np(V), int(to_np(info)[0])
     wr, Vr = oracle.eigh_ref(C)
     scale = max(abs(wr).max(), 1e-300)
@@ -114,15 +118,49 @@ def _eigh_check(hh, C, sweeps_min=0):
     return inf
 
 
-def test_eigh_special_cases(hh):
-    say("eigh special cases")
-    _eigh_check(hh, np.diag([3.0, 1.0, 2.0, 5.0]).astype(np.complex128))        # already diagonal
-    _eigh_check(hh, np.eye(6, dtype=np.complex128))                              # fully degenerate
-    _eigh_check(hh, np.zeros((4, 4), dtype=np.complex128))                       # zero matrix
+@pytest.mark.parametrize("solver", ["jacobi", "tridiag"])
+def test_eigh_special_cases(hh, solver):
+    say(f"eigh special cases {solver}")
+    _eigh_check(hh, np.diag([3.0, 1.0, 2.0, 5.0]).astype(np.complex128), solver=solver)   # already diagonal
+    _eigh_check(hh, np.eye(6, dtype=np.complex128), solver=solver)                         # fully degenerate
+    _eigh_check(hh, np.zeros((4, 4), dtype=np.complex128), solver=solver)                  # zero matrix
     u = np.arange(1, 9) + 1j * np.arange(8)[::-1]
-    _eigh_check(hh, np.outer(u, u.conj()))                                       # rank one
-    C = np.array([[2.0, 1j], [-1j, 2.0]])                                        # purely imaginary coupling
-    _eigh_check(hh, C)
+    _eigh_check(hh, np.outer(u, u.conj()), solver=solver)                                  # rank one
+    C = np.array([[2.0, 1j], [-1j, 2.0]])                                                   # imaginary coupling
+    _eigh_check(hh, C, solver=solver)
+    # a real tridiagonal matrix with one tiny off-diagonal (the QL split test)
+    T = np.diag([4.0, 3.0, 2.0, 1.0, 0.5]) + np.diag([1.0, 1e-300, 0.7, 0.2], 1) + np.diag([1.0, 1e-300, 0.7, 0.2], -1)
+    _eigh_check(hh, T.astype(np.complex128), solver=solver)
+
+
+def test_eigh_tridiag_nonconvergence_reported(hh):
+    import torch
+    n = 8
+    rng = np.random.default_rng(3)
+    X = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
+    C = X @ X.conj().T
+    ev = torch.empty(n, dtype=torch.float64, device="cuda")
+    V = torch.empty((n, n), dtype=torch.complex128, device="cuda")
+    info = torch.empty(1, dtype=torch.int32, device="cuda")
+    hh.hh_eigh_tridiag(n, to_dev(C), ev, V, info, max_iter=0)
+    assert int(to_np(info)[0]) == -1
+    hh.hh_eigh_tridiag(n, to_dev(C), ev, V, info)
+    assert 1 <= int(to_np(info)[0]) <= 40 * n
+
+
+@pytest.mark.parametrize("nt,ny,nx", [(32, 128, 128), (64, 64, 64)])
+def test_pipeline_jacobi_and_tridiag_agree(hh, nt, ny, nx):
+    # the two eigensolvers give the same image to rounding
+    import torch
+    f = gen_stack(nt + 500, nt, ny, nx)
+    out = []
+    for solver in (0, 1):
+        p = hh.Params(nx=nx, ny=ny, nt=nt, k_lo=2, k_hi=nt - 1, eigh_solver=solver)
+        ws = hh.alloc_workspace(hh.workspace_bytes(p))
+        img = torch.empty((ny, nx), dtype=torch.float32, device="cuda")
+        hh.hh_pipeline(p, to_dev(f), img, ws)
+        out.append(to_np(img))
+    assert rel(out[0], out[1]) <= 1e-6
 
 
 def test_eigh_nonconvergence_reported(hh):
