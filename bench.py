@@ -68,7 +68,7 @@ def algorithmic_bytes(kernel: str, launches_per_step: int) -> float:
 # Launch choices for the 1024^2 x 32 workload, picked by the autotuner (hh_autotune)
 # and pinned so that runs are reproducible and comparable with the counter runs
 # below; --autotune reruns the tuner instead.
-PINNED_TUNING = {"fp32": "6,4,512,32", "fp16store": "6,4,256,16", "exact": "6,2,512,16"}
+PINNED_TUNING = {"fp32": "6,4,512,32,0", "fp16store": "6,4,256,16,0", "exact": "6,2,512,16,0"}
 
 # HBM bytes per launch measured with rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE (fetch
 # counter scaled by 2.000 and write by 1.000, the factors a plain 256 MiB copy gives),
@@ -76,10 +76,10 @@ PINNED_TUNING = {"fp32": "6,4,512,32", "fp16store": "6,4,256,16", "exact": "6,2,
 # the pinned launch choices; anything else reports null.
 MEASURED_TRAFFIC = {
     "fingerprint": "c37562606a066655",
-    "fp32": {"tuning": "6,4,512,32", "bytes": {
+    "fp32": {"tuning": "6,4,512,32,0", "bytes": {
         "fresnel_cols": (256.4 + 256.0) * 2 ** 20, "fresnel_rows": (64.3 + 256.0) * 2 ** 20,
         "gram_partial": (256.1 + 8.3) * 2 ** 20, "project_complement": (256.0 + 4.0) * 2 ** 20}},
-    "fp16store": {"tuning": "6,4,256,16", "bytes": {
+    "fp16store": {"tuning": "6,4,256,16,0", "bytes": {
         "fresnel_cols_r16": (64.3 + 32.0) * 2 ** 20, "fresnel_rows": (20.3 + 64.0) * 2 ** 20,
         "gram_partial_r16": (142.8 + 16.5) * 2 ** 20, "project_r16_complement": (136.0 + 4.0) * 2 ** 20,
         "frame_mean": (64.0 + 4.0) * 2 ** 20}},
@@ -158,7 +158,7 @@ def main():
     ap.add_argument("--autotune", action="store_true",
                     help="run the autotuner first (untimed) instead of the pinned launch choices")
     ap.add_argument("--tuning", default=None,
-                    help="launch choices 'rows,cols,pxw,group', e.g. 2,0,512,0 (default: the pinned ones)")
+                    help="launch choices 'rows,cols,pxw,group[,gram_ref]', e.g. 2,0,512,0 (default: the pinned ones)")
     ap.add_argument("--workload", default="stack", choices=["stack", "batched8", "serve"],
                     help="stack: the 1024^2 x 32 headline; batched8: 8 uneven stacks replayed as one HIP graph; "
                          "serve: two simulated cameras through the streaming server")
@@ -203,10 +203,10 @@ def main():
         print("bench: autotuning launch choices (untimed)", file=sys.stderr, flush=True)
         hh.autotune(p, frames[0], ws1, reps=5)
     else:
-        r, c, x, g = (int(v) for v in (args.tuning or PINNED_TUNING.get(args.precision, "0,0,256,0")).split(","))
-        hh.tuning_set(p, fft_rows=r, fft_cols=c, gram_pxw=x, group=g)
+        vals = [int(v) for v in (args.tuning or PINNED_TUNING.get(args.precision, "0,0,256,0")).split(",")]
+        hh.tuning_set(p, *vals)
     tuning = hh.tuning_get(p)
-    tuning_str = ",".join(str(tuning[k]) for k in ("fft_rows", "fft_cols", "gram_pxw", "group"))
+    tuning_str = ",".join(str(tuning[k]) for k in ("fft_rows", "fft_cols", "gram_pxw", "group", "gram_ref"))
     img1 = torch.empty((NY, NX), dtype=torch.float32, device=dev)
     info = torch.empty(1, dtype=torch.int32, device=dev)
     S = max(1, args.streams) if B > 1 else 1

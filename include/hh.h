@@ -322,14 +322,17 @@ void hh_graph_destroy(hh_graph *g);
  *              Shapes 1-6 exist for ny >= 512.
  *   gram_pxw : covariance split-K chunk, pixels per wavefront: 256, 512 or 1024
  *              (FP32 partial sums grow with it).
+ *   gram_ref : reference m of the covariance's exact per-pixel split H = m 1^T + R
+ *              (HH_FP32 form, nt <= 32): 0 = the temporal mean, 1 = the pixel's
+ *              frame-0 value (one lane broadcast instead of a 16-lane sum).
  *   group    : frames per Fresnel group (row pass then column pass), 0 = about
  *              64 MiB of FP32 holograms, at most four times that (the FP16
  *              storage form clamps it to the default, the size of its buffer).
  * The FFT choices and the group apply to every call with the same (nx, ny) on
- * the current device, gram_pxw to the same (nx * ny, nt, precision).
+ * the current device, gram_pxw and gram_ref to the same (nx * ny, nt, precision).
  */
 typedef struct {
-  int32_t fft_rows, fft_cols, gram_pxw, group;
+  int32_t fft_rows, fft_cols, gram_pxw, group, gram_ref;
 } hh_tuning;
 
 /* Choices now in force for *p (defaults where none were set).  Uses nx, ny, nt, precision. */

@@ -10,8 +10,10 @@
 // so C is dominated by one eigenvalue while the components the image keeps sit
 // ~1e-3 below it.  FP32 sums of raw products would leave errors of ~1e-8 of the
 // top eigenvalue, enough to tilt the kept subspace when the boundary gap is
-// small.  Each pixel is therefore split exactly as H = m 1^T + R, m the pixel's
-// temporal mean (any m works: R is formed as H - m), and
+// small.  Each pixel is therefore split exactly as H = m 1^T + R, m a reference
+// value of the pixel (any m works: R is formed as H - m): its temporal mean, or
+// its frame-0 value, which removes the static part as well and costs one DPP
+// row broadcast instead of a 16-lane sum; and
 //   C = (m^H m) 1 1^T + 1 a^T + conj(a) 1^T + R^H R,   a_t = sum_p conj(m_p) R[p][t],
 // with R^H R on MFMA (FP32 sums over at most 512 products per accumulator) and
 // the rank-one terms carried to FP64 every 8 pixels.  Partials are combined in
@@ -54,10 +56,11 @@ __device__ __forceinline__ float sum32(float v) {
 // holds frames f and 16 + f of pixel slot k.  A 16-byte load of lane k covers
 // pixels 8j + 2k, 8j + 2k + 1, so one load instruction reads 64 contiguous bytes
 // of each of 16 frames, and the two MFMA steps of a load take pixels
-// {8j, 8j+2, 8j+4, 8j+6} and {8j+1, 8j+3, 8j+5, 8j+7}.  The 32-frame mean of a
-// pixel is a 16-lane sum of the two values (DPP).  S needs the upper 16x16
-// blocks 00, 01, 11 only; Q all four.  TWO = false when n_t <= 16.
-template <bool TWO>
+// {8j, 8j+2, 8j+4, 8j+6} and {8j+1, 8j+3, 8j+5, 8j+7}.  MEAN: the reference is
+// the temporal mean, a 16-lane sum of the two values (DPP); else frame 0's value,
+// broadcast from lane f = 0 of the row.  S needs the upper 16x16 blocks 00, 01,
+// 11 only; Q all four.  TWO = false when n_t <= 16.
+template <bool TWO, bool MEAN>
 __global__ __launch_bounds__(256) void gram_partial16(const float2 *__restrict__ H, int nt, long long npix,
                                                       int pxw, double *__restrict__ partial) {
   constexpr int D = 32;
@@ -94,7 +97,14 @@ __global__ __launch_bounds__(256) void gram_partial16(const float2 *__restrict__
       for (int e = 0; e < 2; ++e) {
         float2 x0 = e ? make_float2(h0[g].z, h0[g].w) : make_float2(h0[g].x, h0[g].y);
         float2 x1 = e ? make_float2(h1[g].z, h1[g].w) : make_float2(h1[g].x, h1[g].y);
-        const float mr = sum16(x0.x + x1.x) * inv_nt, mi = sum16(x0.y + x1.y) * inv_nt;
+        float mr, mi;
+        if constexpr (MEAN) {
+          mr = sum16(x0.x + x1.x) * inv_nt;
+          mi = sum16(x0.y + x1.y) * inv_nt;
+        } else {
+          mr = dpp<0x150>(x0.x);  // row_newbcast:0 (lane f = 0 holds frame 0)
+          mi = dpp<0x150>(x0.y);
+        }
         mmf += mr * mr + mi * mi;
         if (v0) {
           x0.x -= mr;
@@ -822,12 +832,17 @@ hipError_t launch_gram(const GramLayout &L, const float2 *holo, int nt, long lon
     }
   } else {
     ProfScope ps("gram_partial", s);
-    if (nt <= 16)
-      hipLaunchKernelGGL(gram_partial16<false>, dim3(L.groups), dim3(256), 0, s, holo, nt, npix, L.pxw, partial);
-    else if (nt <= 32)
-      hipLaunchKernelGGL(gram_partial16<true>, dim3(L.groups), dim3(256), 0, s, holo, nt, npix, L.pxw, partial);
-    else
+    const dim3 g(L.groups), b(256);
+    if (nt <= 16) {
+      if (L.ref) hipLaunchKernelGGL((gram_partial16<false, false>), g, b, 0, s, holo, nt, npix, L.pxw, partial);
+      else hipLaunchKernelGGL((gram_partial16<false, true>), g, b, 0, s, holo, nt, npix, L.pxw, partial);
+    } else if (nt <= 32) {
+      if (L.ref) hipLaunchKernelGGL((gram_partial16<true, false>), g, b, 0, s, holo, nt, npix, L.pxw, partial);
+      else hipLaunchKernelGGL((gram_partial16<true, true>), g, b, 0, s, holo, nt, npix, L.pxw, partial);
+    }
+    else {
       hipLaunchKernelGGL(gram_partial64, dim3(L.groups), dim3(256), 0, s, holo, nt, npix, L.pxw, partial);
+    }
   }
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;

@@ -240,7 +240,7 @@ using FftKey = std::tuple<int, int, int>;
 using GramKey = std::tuple<int, long long, int, int>;
 std::mutex g_tune_mu;
 std::map<FftKey, Tune> g_fft_tune;
-std::map<GramKey, int> g_gram_tune;
+std::map<GramKey, std::pair<int, int>> g_gram_tune;  // (pixels per wave, reference of the split)
 
 int current_device() {
   int d = 0;
@@ -254,7 +254,8 @@ Tune get_tune(const hh_params &p) {
   auto f = g_fft_tune.find(FftKey{d, p.nx, p.ny});
   if (f != g_fft_tune.end()) t = f->second;
   auto q = g_gram_tune.find(GramKey{d, (long long)p.nx * p.ny, p.nt, p.precision});
-  t.pxw = q != g_gram_tune.end() ? q->second : kGramPxwMin;
+  t.pxw = q != g_gram_tune.end() ? q->second.first : kGramPxwMin;
+  t.gram_ref = q != g_gram_tune.end() ? q->second.second : 0;
   return t;
 }
 
@@ -262,7 +263,7 @@ void put_tune(const hh_params &p, const Tune &t) {
   const int d = current_device();
   std::lock_guard<std::mutex> g(g_tune_mu);
   g_fft_tune[FftKey{d, p.nx, p.ny}] = t;
-  g_gram_tune[GramKey{d, (long long)p.nx * p.ny, p.nt, p.precision}] = t.pxw;
+  g_gram_tune[GramKey{d, (long long)p.nx * p.ny, p.nt, p.precision}] = {t.pxw, t.gram_ref};
 }
 
 int default_group(const hh_params &p) { return fresnel_group_frames(p.nx, p.ny, 1 << 30, 0); }
@@ -273,6 +274,7 @@ hh_status check_tune(const hh_params &p, const hh_tuning &t) {
   if (t.fft_cols < 0 || t.fft_cols >= ncols) return fail(HH_E_INVALID, "fft_cols=%d: %d shape(s) at ny=%d", t.fft_cols, ncols, p.ny);
   if (t.gram_pxw != 256 && t.gram_pxw != 512 && t.gram_pxw != 1024)
     return fail(HH_E_INVALID, "gram_pxw=%d: must be 256, 512 or 1024", t.gram_pxw);
+  if (t.gram_ref < 0 || t.gram_ref > 1) return fail(HH_E_INVALID, "gram_ref=%d: must be 0 or 1", t.gram_ref);
   if (t.group < 0 || t.group > 4 * default_group(p))
     return fail(HH_E_INVALID, "group=%d: must be in [0, %d] (0 = default)", t.group, 4 * default_group(p));
   return HH_OK;
@@ -335,7 +337,8 @@ hipError_t enqueue_front(const hh_params &p, const Plan *pl, const PipeLayout &L
                          const float2 *holo, StackViews &v, hipStream_t s) {
   const long long npix = (long long)p.nx * p.ny;
   const Tune tu = get_tune(p);
-  const GramLayout gl = gram_layout(p.nt, npix, tu.pxw);  // offsets in L are sized for the smallest chunk
+  GramLayout gl = gram_layout(p.nt, npix, tu.pxw);  // offsets in L are sized for the smallest chunk
+  gl.ref = tu.gram_ref;
   double *part = reinterpret_cast<double *>(ws + L.part), *part2 = reinterpret_cast<double *>(ws + L.part2);
   v.cov = reinterpret_cast<double *>(ws + L.cov);
   v.part2 = part2;
@@ -504,7 +507,8 @@ hh_status hh_covariance(const hh_params *p, const float *holo, double *cov, void
     return fail(HH_E_WORKSPACE, "covariance workspace: need %zu bytes (256-byte aligned), got %zu", need, ws_bytes);
   const long long npix = (long long)p->nx * p->ny;
   const GramLayout g = gram_layout(p->nt, npix);                     // sizes the workspace
-  const GramLayout gl = gram_layout(p->nt, npix, get_tune(*p).pxw);  // the launch
+  GramLayout gl = gram_layout(p->nt, npix, get_tune(*p).pxw);  // the launch
+  gl.ref = get_tune(*p).gram_ref;
   char *ws = static_cast<char *>(workspace);
   hipError_t e = launch_gram(gl, reinterpret_cast<const float2 *>(holo), p->nt, npix, reinterpret_cast<double *>(ws),
                              reinterpret_cast<double *>(ws + align_up(g.partial_bytes)), cov, (hipStream_t)stream,
@@ -745,7 +749,7 @@ hh_status hh_tuning_get(const hh_params *p, hh_tuning *t) {
   hh_status st;
   if ((st = check_shape(p))) return st;
   const Tune tu = get_tune(*p);
-  *t = hh_tuning{tu.rows, tu.cols, tu.pxw, tu.group};
+  *t = hh_tuning{tu.rows, tu.cols, tu.pxw, tu.group, tu.gram_ref};
   return HH_OK;
 }
 
@@ -753,7 +757,7 @@ hh_status hh_tuning_set(const hh_params *p, const hh_tuning *t) {
   if (!p || !t) return fail(HH_E_INVALID, "params and tuning must be non-NULL");
   hh_status st;
   if ((st = check_shape(p)) || (st = check_tune(*p, *t))) return st;
-  put_tune(*p, Tune{t->fft_rows, t->fft_cols, t->gram_pxw, t->group});
+  put_tune(*p, Tune{t->fft_rows, t->fft_cols, t->gram_pxw, t->group, t->gram_ref});
   return HH_OK;
 }
 
@@ -812,7 +816,8 @@ hh_status hh_autotune(const hh_params *p, const uint16_t *frames, void *workspac
       {&Tune::rows, p->nx >= 512 ? std::vector<int>{0, 1, 2, 3, 4, 5, 6, 7} : std::vector<int>{0}},
       {&Tune::cols, p->ny >= 512 ? std::vector<int>{0, 1, 2, 3, 4, 5, 6} : std::vector<int>{0}},
       {&Tune::group, {0, std::max(1, dg / 2), std::max(1, dg / 4), std::min(2 * dg, p->nt), std::min(4 * dg, p->nt)}},
-      {&Tune::pxw, {256, 512, 1024}}};
+      {&Tune::pxw, {256, 512, 1024}},
+      {&Tune::gram_ref, {0, 1}}};
   for (auto &ax : axes) {
     for (int val : ax.second) {
       if (st != HH_OK) break;
@@ -831,7 +836,7 @@ hh_status hh_autotune(const hh_params *p, const uint16_t *frames, void *workspac
   if (img) (void)hipFree(img);
   if (ev0) (void)hipEventDestroy(ev0);
   if (ev1) (void)hipEventDestroy(ev1);
-  if (st == HH_OK && best) *best = hh_tuning{cur.rows, cur.cols, cur.pxw, cur.group};
+  if (st == HH_OK && best) *best = hh_tuning{cur.rows, cur.cols, cur.pxw, cur.group, cur.gram_ref};
   return st;
 }
 

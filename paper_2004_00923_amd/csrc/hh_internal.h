@@ -62,6 +62,7 @@ struct GramLayout {
   int nb = 1;              // 32-frame blocks (1 or 2)
   int D = 32;              // 32 * nb
   int pxw = 256;           // pixels per wave (split-K chunk); FP32 sums of <= 2 pxw products
+  int ref = 0;             // FP32 form, n_t <= 32: reference of the split, 0 = temporal mean, 1 = frame 0
   long long chunks = 0;    // pixel chunks of pxw pixels (one per wave)
   int groups = 0;          // workgroups of the partial kernel
   int groups2 = 0;         // second-level partial count
@@ -73,6 +74,7 @@ struct Tune {
   int cols = 0;      // column-FFT launch shape (0..2)
   int pxw = 256;     // Gram pixels per wave: 256, 512 or 1024
   int group = 0;     // frames per Fresnel group, 0 = about 64 MiB of holograms
+  int gram_ref = 0;  // reference of the covariance's mean split (FP32 form): 0 temporal mean, 1 frame 0
 };
 constexpr int kGramPxwMin = 256;  // the workspace is sized for the smallest split-K chunk
 GramLayout gram_layout(int nt, long long npix, int pxw = kGramPxwMin);

@@ -162,13 +162,13 @@ def test_status_strings():
 def test_tuning_validation_and_roundtrip():
     hh.tuning_reset()
     p = hh.Params(nx=1024, ny=1024, nt=32, k_lo=2, k_hi=31)
-    assert hh.tuning_get(p) == {"fft_rows": 0, "fft_cols": 0, "gram_pxw": 256, "group": 0}
-    hh.tuning_set(p, fft_rows=1, fft_cols=2, gram_pxw=1024, group=4)
-    assert hh.tuning_get(p) == {"fft_rows": 1, "fft_cols": 2, "gram_pxw": 1024, "group": 4}
+    assert hh.tuning_get(p) == {"fft_rows": 0, "fft_cols": 0, "gram_pxw": 256, "group": 0, "gram_ref": 0}
+    hh.tuning_set(p, fft_rows=1, fft_cols=2, gram_pxw=1024, group=4, gram_ref=1)
+    assert hh.tuning_get(p) == {"fft_rows": 1, "fft_cols": 2, "gram_pxw": 1024, "group": 4, "gram_ref": 1}
     # FFT choices follow (nx, ny); the split-K chunk follows (nx * ny, nt, precision)
     q = hh.Params(nx=1024, ny=1024, nt=16, k_lo=2, k_hi=15)
     assert hh.tuning_get(q)["fft_rows"] == 1 and hh.tuning_get(q)["gram_pxw"] == 256
-    for bad in ({"fft_rows": 8}, {"fft_cols": 7}, {"gram_pxw": 300}, {"group": -1}, {"group": 33}):
+    for bad in ({"fft_rows": 8}, {"fft_cols": 7}, {"gram_pxw": 300}, {"group": -1}, {"group": 33}, {"gram_ref": 2}):
         with pytest.raises(hh.HHError) as ei:
             hh.tuning_set(p, **bad)
         assert ei.value.status == hh.HH_E_INVALID

@@ -46,16 +46,16 @@ def case(hh):
                                                  (0, 1, 256, 0), (0, 2, 256, 0), (0, 3, 256, 0), (0, 4, 256, 0),
                                                  (0, 5, 256, 0), (0, 6, 256, 0), (0, 0, 512, 0), (0, 0, 1024, 0),
                                                  (0, 0, 256, 3), (2, 2, 1024, 1), (6, 5, 512, 32), (7, 6, 256, 5)])
-@pytest.mark.parametrize("precision", ["fp32", "fp16store"])
-def test_every_launch_choice_meets_the_bar(hh, case, rows, cols, pxw, group, precision):
+@pytest.mark.parametrize("precision,gram_ref", [("fp32", 0), ("fp32", 1), ("fp16store", 0)])
+def test_every_launch_choice_meets_the_bar(hh, case, rows, cols, pxw, group, precision, gram_ref):
     f, fd, ref = case
     p = hh.Params(nx=1024, ny=512, nt=32, k_lo=2, k_hi=31, precision=hh.PRECISIONS[precision])
-    hh.tuning_set(p, fft_rows=rows, fft_cols=cols, gram_pxw=pxw, group=group)
+    hh.tuning_set(p, fft_rows=rows, fft_cols=cols, gram_pxw=pxw, group=group, gram_ref=gram_ref)
     try:
         e = rel(_run(hh, p, fd), ref)
     finally:
         hh.tuning_reset()
-    say(f"tuning rows={rows} cols={cols} pxw={pxw} group={group} {precision}: image {e:.2e}")
+    say(f"tuning rows={rows} cols={cols} pxw={pxw} group={group} ref={gram_ref} {precision}: image {e:.2e}")
     assert e <= (IMG_TOL if precision == "fp32" else 1e-3)
 
 
@@ -68,3 +68,23 @@ def test_autotune_picks_a_valid_choice(hh, case):
     assert hh.tuning_get(p) == best
     assert rel(_run(hh, p, fd), ref) <= IMG_TOL
     hh.tuning_reset()
+
+
+@pytest.mark.parametrize("nt,ny,nx", [(32, 128, 128), (16, 64, 64), (31, 32, 64), (3, 8, 8), (32, 1024, 1024)])
+def test_frame0_reference_covariance(hh, nt, ny, nx):
+    # the covariance with the frame-0 reference of the split meets the FP32 bar on C
+    import torch
+    f = gen_stack(nt * 3 + nx, nt, ny, nx)
+    H32 = oracle.fresnel_ref(f, LAM, Z, PITCH).astype(np.complex64)
+    C_ref = oracle.covariance_ref(H32.astype(np.complex128))
+    p = hh.Params(nx=nx, ny=ny, nt=nt, k_lo=0, k_hi=nt - 1)
+    hh.tuning_set(p, gram_ref=1)
+    try:
+        ws = hh.alloc_workspace(hh.covariance_workspace_bytes(p))
+        C = torch.empty((nt, nt), dtype=torch.complex128, device="cuda")
+        hh.hh_covariance(p, to_dev(H32), C, ws)
+        e = rel(to_np(C), C_ref)
+    finally:
+        hh.tuning_reset()
+    say(f"frame-0 reference covariance {nt}x{ny}x{nx}: {e:.2e}")
+    assert e <= 2e-6
