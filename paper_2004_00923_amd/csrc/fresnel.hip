@@ -45,6 +45,21 @@ struct ColSlot {
   __device__ __forceinline__ int operator()(int e) const { return fft_pad(e) * W + c; }
 };
 
+// Eight floats into the LDS staging area: two 16-byte stores when the row's area
+// starts 16-byte aligned (lanes 32 bytes apart then touch distinct bank groups),
+// else eight 4-byte stores.
+template <bool ALIGNED16>
+__device__ __forceinline__ void stage8(float *dst, const float (&x)[8]) {
+  if constexpr (ALIGNED16) {
+    float4 *d4 = reinterpret_cast<float4 *>(dst);
+    d4[0] = make_float4(x[0], x[1], x[2], x[3]);
+    d4[1] = make_float4(x[4], x[5], x[6], x[7]);
+  } else {
+#pragma unroll
+    for (int e = 0; e < 8; ++e) dst[e] = x[e];
+  }
+}
+
 // Input of the row pass: the uint16 frames, the frames minus a float frame
 // (the stack's temporal mean), or one float frame.
 enum { kInU16 = 0, kInU16MinusMean = 1, kInF32 = 2 };
@@ -65,7 +80,7 @@ __global__ __launch_bounds__(ROWS *(N / fft_e(N, EP))) void fresnel_rows(
   const float2 cy = chirp_y[live ? row : 0];
   if constexpr (FftCfg<N, EP>::P > 1) {
     typedef typename std::conditional<SPLIT, float, float2>::type Slot;
-    __shared__ Slot lds[ROWS * FftCfg<N, EP>::LDSN];
+    __shared__ __align__(16) Slot lds[ROWS * FftCfg<N, EP>::LDSN];
     // The row arrives through LDS: 16-byte coalesced loads of 8 pixels each are
     // written to the row's LDS area as floats, then every thread reads its
     // elements t + T i in FFT order (the FFT's first pass then reuses the area).
@@ -98,8 +113,7 @@ __global__ __launch_bounds__(ROWS *(N / fft_e(N, EP))) void fresnel_rows(
 #pragma unroll
         for (int e = 0; e < 8; ++e) x[e] = 0.0f;
       }
-#pragma unroll
-      for (int e = 0; e < 8; ++e) stage[8 * c + e] = x[e];
+      stage8<(FftCfg<N, EP>::LDSN * sizeof(Slot)) % 16 == 0>(stage + 8 * c, x);
     }
     __syncthreads();
 #pragma unroll
@@ -220,7 +234,7 @@ __global__ __launch_bounds__(ROWS *(N / fft_e(N, EP))) void fresnel_rows_persist
   constexpr int E = FftCfg<N, EP>::E, T = FftCfg<N, EP>::T, L = N / 8 / T > 0 ? N / 8 / T : 1;
   static_assert(FftCfg<N, EP>::P > 1 && N / 8 >= T, "persistent rows need an LDS exchange and 8 pixels per thread");
   typedef typename std::conditional<SPLIT, float, float2>::type Slot;
-  __shared__ Slot lds[ROWS * FftCfg<N, EP>::LDSN];
+  __shared__ __align__(16) Slot lds[ROWS * FftCfg<N, EP>::LDSN];
   const int t = threadIdx.x % T, r = threadIdx.x / T;
   float *stage = reinterpret_cast<float *>(lds + r * FftCfg<N, EP>::LDSN);
   const int groups = (ny + ROWS - 1) / ROWS, items = groups * nframes;
@@ -270,8 +284,7 @@ __global__ __launch_bounds__(ROWS *(N / fft_e(N, EP))) void fresnel_rows_persist
 #pragma unroll
         for (int e = 0; e < 8; ++e) x[e] = 0.0f;
       }
-#pragma unroll
-      for (int e = 0; e < 8; ++e) stage[8 * c + e] = x[e];
+      stage8<(FftCfg<N, EP>::LDSN * sizeof(Slot)) % 16 == 0>(stage + 8 * c, x);
     }
     __syncthreads();
     const float2 cy = chirp_y[live ? row : 0];
