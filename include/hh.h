@@ -94,8 +94,13 @@ enum {
 enum {
   HH_PROJ_AUTO = 0,        /* the cheaper of the two below */
   HH_PROJ_DIRECT = 1,      /* sum over kept k of |sum_t H[p][t] V[t][k]|^2, FP32 */
-  HH_PROJ_COMPLEMENT = 2   /* sum_t |H[p][t]|^2 - sum over dropped k of |.|^2, FP64
+  HH_PROJ_COMPLEMENT = 2,  /* sum_t |H[p][t]|^2 - sum over dropped k of |.|^2, FP64
                               (V unitary, Eq. (5); exact reformulation) */
+  HH_PROJ_FIRST = 3        /* projection first: Y_k = Eq. (1) applied to J_k = sum_t V[t][k] I_t
+                              (Eq. (1) is linear in the frame), M = sum over kept k of |Y_k|^2:
+                              K transforms of combined frames, the holograms are never formed.
+                              Requires precision HH_EXACT (C from the frames as well) and an
+                              entry point that starts from frames (see hh_project_frames) */
 };
 
 typedef struct {
@@ -118,6 +123,29 @@ size_t hh_workspace_bytes(const hh_params *p);
 
 /* Bytes of device workspace hh_covariance needs for *p (0 if *p is invalid). */
 size_t hh_covariance_workspace_bytes(const hh_params *p);
+
+/* Bytes of device workspace hh_project_frames needs for *p (0 if *p is invalid). */
+size_t hh_project_frames_workspace_bytes(const hh_params *p);
+
+/*
+ * Steps (d)+(e), Eq. (6)-(7), evaluated from the frames (projection first):
+ * by linearity of Eq. (1) the projected hologram of component k is the Fresnel
+ * transform of J_k = sum_t V[t][k] I_t, so
+ *   image[p] = sum_{k = k_lo..k_hi} |Fresnel(J_k)[p]|^2,
+ * the same image as hh_project_render on hh_fresnel's holograms, computed with
+ * K = k_hi - k_lo + 1 transforms instead of nt and without forming H.
+ *   frames : uint16 [nt][ny][nx], 16-byte aligned.
+ *   evecs  : complex128 [nt][nt], evecs[t][k] = V[t][k] (any complex matrix; the
+ *            eigenvectors of Eq. (5) in the intended use), 16-byte aligned.
+ *   image  : float32 [ny][nx], 8-byte aligned.
+ *   workspace: hh_project_frames_workspace_bytes(p) bytes, 256-byte aligned
+ *            (K row-transformed components and partial images).
+ * Uses the optics, nx, ny, nt, k_lo, k_hi of *p (precision and proj_mode are
+ * not read).  J_k is summed in FP32 around each pixel's frame-0 value (exact
+ * integer differences), the transforms and |.|^2 are FP32.  Errors as hh_pipeline.
+ */
+hh_status hh_project_frames(const hh_params *p, const uint16_t *frames, const double *evecs, float *image,
+                            void *workspace, size_t ws_bytes, void *stream);
 
 /*
  * Step (a), Eq. (1): Fresnel holograms of `nframes` frames.
@@ -317,8 +345,8 @@ void hh_graph_destroy(hh_graph *g);
  *              group (fewer where the LDS does not hold them); 1 = 16 points, half
  *              as many columns; 2 = 32 points per thread; 3 and 4 = shapes 0 and 2
  *              with the split exchange; 5 and 6 = shapes 0 and 3 as a persistent grid
- *              (one group per compute unit) that loads the next strip while
- *              transforming the current one.
+ *              (as many groups as the compute units hold) that loads the next strip
+ *              while transforming the current one.
  *              Shapes 1-6 exist for ny >= 512.
  *   gram_pxw : covariance split-K chunk, pixels per wavefront: 256, 512 or 1024
  *              (FP32 partial sums grow with it).

@@ -188,3 +188,50 @@ def svd_filter_ref(holo: np.ndarray, V: np.ndarray, k_lo: int, k_hi: int) -> np.
     Vk = np.asarray(V, dtype=np.complex128)[:, k_lo:k_hi + 1]
     Hf = (Hm @ Vk) @ Vk.conj().T
     return Hf.T.reshape(nt, ny, nx)
+
+
+# ----------------------------------------------------------------------------
+# Projection first: the covariance from the frames and the image from combined
+# frames (a reformulation of steps (b), (d) and (e) that never forms H)
+# ----------------------------------------------------------------------------
+
+def covariance_frames_ref(frames: np.ndarray) -> np.ndarray:
+    """C of Eq. (4) evaluated from the interferograms: C = N_pix I^T I.
+
+    With the unit-modulus input chirp c and the unnormalised DFT F (F^H F =
+    N_pix Id), H_t = F(c I_t) gives conj(H_s)^T H_t = N_pix sum_p I_s[p] I_t[p].
+    The integer Gram is formed exactly in int64 (products below 2^32, sums below
+    2^63 for the supported sizes), then scaled; returns complex128 (n_t, n_t)
+    with zero imaginary part.
+    """
+    x = np.asarray(frames)
+    nt, ny, nx = x.shape
+    Im = x.reshape(nt, ny * nx).astype(np.int64)
+    G = Im @ Im.T
+    return (G.astype(np.float64) * float(ny * nx)).astype(np.complex128)
+
+
+def project_first_ref(frames: np.ndarray, V: np.ndarray, wavelength: float, distance: float, pitch: float,
+                      k_lo: int, k_hi: int) -> np.ndarray:
+    """Image of Eq. (7) with the projection taken before the propagation.
+
+    Eq. (1) is linear in the frame, so column k of H V (Eq. (6)) is the Fresnel
+    hologram of the combined frame J_k = sum_t V[t, k] I_t:
+        M[y, x] = sum_{k = k_lo..k_hi} |Fresnel(J_k)[y, x]|^2.
+    Returns float64 (n_y, n_x).
+    """
+    x = np.asarray(frames)
+    nt, ny, nx = x.shape
+    Vk = np.asarray(V, dtype=np.complex128)[:, k_lo:k_hi + 1]
+    J = (Vk.T @ x.reshape(nt, ny * nx).astype(np.complex128)).reshape(-1, ny, nx)
+    Y = fresnel_ref(J, wavelength, distance, pitch)
+    return np.sum(Y.real ** 2 + Y.imag ** 2, axis=0)
+
+
+def pipeline_first_ref(frames: np.ndarray, wavelength: float, distance: float, pitch: float,
+                       k_lo: int, k_hi: int) -> dict:
+    """The projection-first path: C from the frames, Eq. (5), image from combined frames."""
+    C = covariance_frames_ref(frames)
+    lam, V = eigh_ref(C)
+    M = project_first_ref(frames, V, wavelength, distance, pitch, k_lo, k_hi)
+    return dict(cov=C, evals=lam, evecs=V, image=M)

@@ -152,9 +152,8 @@ __global__ __launch_bounds__(ROWS *(N / fft_e(N, EP))) void fresnel_rows(
 // R16: instead of writing the column FFT back in place, write it scaled by
 // `scale` and rounded to FP16 (round to nearest even) into r16 [frames][N][nx].
 template <int N, int EP, int W, bool R16, bool SPLIT>
-__global__ __launch_bounds__(W *(N / fft_e(N, EP))) void fresnel_cols(float2 *__restrict__ data, int nx,
-                                                               const float2 *__restrict__ tw, h2 *__restrict__ r16,
-                                                               float scale) {
+__global__ __launch_bounds__(W *(N / fft_e(N, EP))) void fresnel_cols(float2 *__restrict__ data, int nx, const float2 *__restrict__ tw, h2 *__restrict__ r16,
+                  float scale) {
   constexpr int E = FftCfg<N, EP>::E, T = FftCfg<N, EP>::T;
   const int c = threadIdx.x % W;
   const int t = threadIdx.x / W;
@@ -452,7 +451,17 @@ hipError_t cols_launch(const Plan &pl, int nframes, float2 *data, h2 *r16, float
 template <int N, int EP, int W, bool SPLIT = false>
 hipError_t cols_persist_launch(const Plan &pl, int nframes, float2 *data, h2 *r16, float scale, hipStream_t s) {
   const int items = (pl.nx + W - 1) / W * nframes;
-  const int grid = items < pl.cus ? items : pl.cus;  // one resident group per compute unit (LDS, registers)
+  // as many groups as the compute units hold at once (LDS, registers)
+  static int per_cu = 0;
+  if (per_cu == 0) {
+    int occ = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, fresnel_cols_persist<N, EP, W, false, SPLIT>,
+                                                     W * FftCfg<N, EP>::T, 0) != hipSuccess || occ < 1)
+      occ = 1;
+    per_cu = occ;
+  }
+  const int resident = per_cu * pl.cus;
+  const int grid = items < resident ? items : resident;
   dim3 g(grid), block(W * FftCfg<N, EP>::T);
   if (r16)
     hipLaunchKernelGGL((fresnel_cols_persist<N, EP, W, true, SPLIT>), g, block, 0, s, data, pl.nx, nframes, pl.tw_y,

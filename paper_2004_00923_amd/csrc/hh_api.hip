@@ -210,7 +210,7 @@ hh_status check_select(const hh_params *p) {
   if (!(0 <= p->k_lo && p->k_lo <= p->k_hi && p->k_hi < p->nt))
     return fail(HH_E_INVALID, "kept range k_lo=%d k_hi=%d must satisfy 0 <= k_lo <= k_hi < nt=%d", p->k_lo,
                 p->k_hi, p->nt);
-  if (p->proj_mode < HH_PROJ_AUTO || p->proj_mode > HH_PROJ_COMPLEMENT)
+  if (p->proj_mode < HH_PROJ_AUTO || p->proj_mode > HH_PROJ_FIRST)
     return fail(HH_E_INVALID, "proj_mode=%d unknown", p->proj_mode);
   return HH_OK;
 }
@@ -224,6 +224,17 @@ hh_status check_precision(const hh_params *p, bool from_frames) {
     return fail(HH_E_UNSUPPORTED, "precision form %d is built for nt <= 32 (nt=%d)", p->precision, p->nt);
   if ((p->precision == HH_FP16_STORE || p->precision == HH_EXACT) && !from_frames)
     return fail(HH_E_UNSUPPORTED, "precision form %d applies to entry points that start from frames", p->precision);
+  if (p->proj_mode == HH_PROJ_FIRST && !from_frames)
+    return fail(HH_E_UNSUPPORTED, "HH_PROJ_FIRST applies to entry points that start from frames");
+  if (p->proj_mode == HH_PROJ_FIRST && p->precision != HH_EXACT)
+    return fail(HH_E_INVALID, "HH_PROJ_FIRST needs precision HH_EXACT (covariance from the frames)");
+  return HH_OK;
+}
+
+// the image-from-holograms entry points take every projection mode but HH_PROJ_FIRST
+hh_status check_holo_proj(const hh_params *p) {
+  if (p->proj_mode == HH_PROJ_FIRST)
+    return fail(HH_E_UNSUPPORTED, "HH_PROJ_FIRST starts from frames (hh_project_frames, hh_pipeline)");
   return HH_OK;
 }
 
@@ -282,8 +293,9 @@ hh_status check_tune(const hh_params &p, const hh_tuning &t) {
 
 struct PipeLayout {
   GramLayout g;
-  bool r16 = false;  // FP16 storage form
-  size_t holo = 0, r16buf = 0, group = 0, mean = 0, m = 0;
+  bool r16 = false;    // FP16 storage form
+  bool first = false;  // projection first: the hologram area holds the K row-transformed components
+  size_t holo = 0, r16buf = 0, group = 0, mean = 0, m = 0, eparts = 0;
   size_t part = 0, part2 = 0, cov = 0, evals = 0, evecs = 0, info = 0, total = 0;
 };
 
@@ -302,6 +314,11 @@ PipeLayout pipe_layout(const hh_params *p, bool with_holo = true) {
   } else {
     L.holo = o;
     if (with_holo) o = align_up(o + (size_t)p->nt * npix * sizeof(float2));
+  }
+  L.first = with_holo && p->proj_mode == HH_PROJ_FIRST;
+  if (L.first) {
+    L.eparts = o;
+    o = align_up(o + (size_t)kMaxEnergyChunks * npix * sizeof(float));
   }
   L.part = o; o = align_up(o + L.g.partial_bytes);
   L.part2 = o; o = align_up(o + L.g.partial2_bytes);
@@ -331,6 +348,11 @@ struct StackViews {
   double *cov = nullptr;
   const double *part2 = nullptr;  // covariance partials the eigensolver assembles into cov
   int g2 = 0, D = 0;
+  // projection first: the frames, the component and partial-image areas, the plan's tables
+  const uint16_t *frames = nullptr;
+  float2 *inter = nullptr;
+  float *eparts = nullptr;
+  const Plan *pl = nullptr;
 };
 
 hipError_t enqueue_front(const hh_params &p, const Plan *pl, const PipeLayout &L, char *ws, const uint16_t *frames,
@@ -355,6 +377,13 @@ hipError_t enqueue_front(const hh_params &p, const Plan *pl, const PipeLayout &L
     if (e != hipSuccess) return e;
     return launch_gram_r16(gl, r, m, p.nt, npix, v.inv_s, part, part2, v.cov, s, false);
   }
+  if (L.first) {  // C from the frames; the transforms wait for V
+    v.frames = frames;
+    v.inter = reinterpret_cast<float2 *>(ws + L.holo);
+    v.eparts = reinterpret_cast<float *>(ws + L.eparts);
+    v.pl = pl;
+    return launch_gram_u16(gl, frames, p.nt, npix, part, part2, v.cov, s, false);
+  }
   if (frames) {
     float2 *H = reinterpret_cast<float2 *>(ws + L.holo);
     hipError_t e = launch_fresnel(*pl, tu, frames, p.nt, H, s);
@@ -369,6 +398,9 @@ hipError_t enqueue_front(const hh_params &p, const Plan *pl, const PipeLayout &L
 
 hipError_t enqueue_back(const hh_params &p, const StackViews &v, const double *V, float *image, hipStream_t s) {
   const long long npix = (long long)p.nx * p.ny;
+  // C = N_pix I^T I is real symmetric, so the solver's eigenvectors are real: Re V suffices
+  if (v.inter)
+    return launch_project_frames(*v.pl, v.frames, p.nt, V, p.k_lo, p.k_hi, true, v.inter, v.eparts, image, s);
   if (v.r16) return launch_project_r16(v.r16, v.m, v.inv_s, p.nt, npix, V, p.k_lo, p.k_hi, p.proj_mode, image, s);
   return launch_project(v.H, p.nt, npix, V, p.k_lo, p.k_hi, p.proj_mode, image, s);
 }
@@ -570,7 +602,7 @@ hh_status hh_eigh(int32_t nt, const double *cov, double *evals, double *evecs, i
 
 hh_status hh_svd_filter(const hh_params *p, const float *holo, const double *evecs, float *out, void *stream) {
   hh_status st;
-  if ((st = check_stack(p)) || (st = check_select(p))) return st;
+  if ((st = check_stack(p)) || (st = check_select(p)) || (st = check_holo_proj(p))) return st;
   if (!holo || !evecs || !out) return fail(HH_E_INVALID, "holo, evecs, out must be non-NULL");
   if (!aligned(holo, 16) || !aligned(evecs, 16) || !aligned(out, 16))
     return fail(HH_E_INVALID, "holo/evecs/out must be 16-byte aligned");
@@ -596,9 +628,39 @@ hh_status hh_project_render(const hh_params *p, const float *holo, const double 
   return HH_OK;
 }
 
+size_t hh_project_frames_workspace_bytes(const hh_params *p) {
+  if (check_stack(p) || check_select(p)) return 0;
+  const long long npix = (long long)p->nx * p->ny;
+  const int K = p->k_hi - p->k_lo + 1;
+  return align_up((size_t)K * npix * sizeof(float2)) + align_up((size_t)kMaxEnergyChunks * npix * sizeof(float));
+}
+
+hh_status hh_project_frames(const hh_params *p, const uint16_t *frames, const double *evecs, float *image,
+                            void *workspace, size_t ws_bytes, void *stream) {
+  hh_status st;
+  if ((st = check_optics(p)) || (st = check_stack(p)) || (st = check_select(p))) return st;
+  if (!frames || !evecs || !image) return fail(HH_E_INVALID, "frames, evecs, image must be non-NULL");
+  if (!aligned(frames, 16) || !aligned(evecs, 16) || !aligned(image, 8))
+    return fail(HH_E_INVALID, "frames/evecs/image misaligned");
+  const size_t need = hh_project_frames_workspace_bytes(p);
+  if (!workspace || ws_bytes < need || !aligned(workspace, 256))
+    return fail(HH_E_WORKSPACE, "projection workspace: need %zu bytes (256-byte aligned), got %zu", need, ws_bytes);
+  const Plan *pl = get_plan(*p);
+  if (!pl) return HH_E_DEVICE;
+  const long long npix = (long long)p->nx * p->ny;
+  const int K = p->k_hi - p->k_lo + 1;
+  char *ws = static_cast<char *>(workspace);
+  hipError_t e = launch_project_frames(*pl, frames, p->nt, evecs, p->k_lo, p->k_hi, false,
+                                       reinterpret_cast<float2 *>(ws),
+                                       reinterpret_cast<float *>(ws + align_up((size_t)K * npix * sizeof(float2))),
+                                       image, (hipStream_t)stream);
+  if (e != hipSuccess) return device_fail(e, "hh_project_frames");
+  return HH_OK;
+}
+
 hh_status hh_fourier_render(const hh_params *p, const float *holo, float *image, void *stream) {
   hh_status st;
-  if ((st = check_stack(p)) || (st = check_select(p))) return st;
+  if ((st = check_stack(p)) || (st = check_select(p)) || (st = check_holo_proj(p))) return st;
   if (!holo || !image) return fail(HH_E_INVALID, "holo, image must be non-NULL");
   if (!aligned(holo, 16) || !aligned(image, 8)) return fail(HH_E_INVALID, "holo/image misaligned");
   const double *W = get_dft_basis(p->nt);

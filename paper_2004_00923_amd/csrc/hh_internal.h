@@ -120,6 +120,13 @@ hipError_t launch_project(const float2 *holo, int nt, long long npix, const doub
 // FP16 storage form of steps (d)+(e): H = m + r16 * inv_s
 hipError_t launch_project_r16(const h2 *r16, const float2 *m, float inv_s, int nt, long long npix, const double *V,
                               int k_lo, int k_hi, int mode, float *image, hipStream_t s);
+// Projection-first image from the frames (needs the plan's tables): inter holds
+// K = k_hi - k_lo + 1 row-transformed components (complex64 [K][ny][nx]), eparts
+// kMaxEnergyChunks partial images (float [chunks][ny][nx]).  real_v: read Re V only.
+constexpr int kMaxEnergyChunks = 8;
+int project_frames_chunks(int nx, int ny, int K, int cus);
+hipError_t launch_project_frames(const Plan &pl, const uint16_t *frames, int nt, const double *V, int k_lo, int k_hi,
+                                 bool real_v, float2 *inter, float *eparts, float *image, hipStream_t s);
 // SVD-filtered stack, Eq. (3)
 hipError_t launch_svd_filter(const float2 *holo, int nt, long long npix, const double *V, int k_lo, int k_hi,
                              int mode, float2 *out, hipStream_t s);

@@ -17,7 +17,9 @@ LIB_PATH = os.path.join(HERE, "libhh.so")
 
 HH_OK, HH_E_INVALID, HH_E_UNSUPPORTED, HH_E_WORKSPACE, HH_E_DEVICE, HH_E_NOT_CONVERGED = range(6)
 HH_FP32, HH_BF16, HH_FP16, HH_BF16X3, HH_FP16X3, HH_FP8E4M3, HH_FP16_STORE, HH_EXACT = range(8)
-HH_PROJ_AUTO, HH_PROJ_DIRECT, HH_PROJ_COMPLEMENT = range(3)
+HH_PROJ_AUTO, HH_PROJ_DIRECT, HH_PROJ_COMPLEMENT, HH_PROJ_FIRST = range(4)
+PROJ_MODES = {"auto": HH_PROJ_AUTO, "direct": HH_PROJ_DIRECT, "complement": HH_PROJ_COMPLEMENT,
+              "first": HH_PROJ_FIRST}
 
 PRECISIONS = {"fp32": HH_FP32, "bf16": HH_BF16, "fp16": HH_FP16, "bf16x3": HH_BF16X3,
               "fp16x3": HH_FP16X3, "fp8e4m3": HH_FP8E4M3, "fp16store": HH_FP16_STORE, "exact": HH_EXACT}
@@ -97,6 +99,8 @@ SIGNATURES = {
     "hh_eigh_ex": (ctypes.c_int32, [ctypes.c_int32, _P, _P, _P, _P, ctypes.c_int32, _P]),
     "hh_eigh_tridiag": (ctypes.c_int32, [ctypes.c_int32, _P, _P, _P, _P, ctypes.c_int32, _P]),
     "hh_project_render": (ctypes.c_int32, [ctypes.POINTER(hh_params), _P, _P, _P, _P]),
+    "hh_project_frames_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(hh_params)]),
+    "hh_project_frames": (ctypes.c_int32, [ctypes.POINTER(hh_params), _P, _P, _P, _P, ctypes.c_size_t, _P]),
     "hh_pipeline": (ctypes.c_int32, [ctypes.POINTER(hh_params), _P, _P, _P, _P, _P, _P, ctypes.c_size_t, _P]),
     "hh_fourier_render": (ctypes.c_int32, [ctypes.POINTER(hh_params), _P, _P, _P]),
     "hh_svd_filter": (ctypes.c_int32, [ctypes.POINTER(hh_params), _P, _P, _P, _P]),
@@ -239,6 +243,22 @@ def hh_project_render(p: Params, holo, evecs, image, stream=None):
     _dev_tensor(evecs, torch.complex128, (p.nt, p.nt), "evecs")
     _dev_tensor(image, torch.float32, (p.ny, p.nx), "image")
     _check(lib().hh_project_render(ctypes.byref(p.c()), _ptr(holo), _ptr(evecs), _ptr(image), _stream(stream)))
+    return image
+
+
+def project_frames_workspace_bytes(p: Params) -> int:
+    return int(lib().hh_project_frames_workspace_bytes(ctypes.byref(p.c())))
+
+
+def hh_project_frames(p: Params, frames, evecs, image, workspace, stream=None):
+    """Steps (d)+(e) from the frames (projection first): frames uint16 [nt, ny, nx],
+    evecs complex128 [nt, nt] -> image float32 [ny, nx]; see include/hh.h."""
+    import torch
+    _dev_tensor(frames, torch.uint16, (p.nt, p.ny, p.nx), "frames")
+    _dev_tensor(evecs, torch.complex128, (p.nt, p.nt), "evecs")
+    _dev_tensor(image, torch.float32, (p.ny, p.nx), "image")
+    _check(lib().hh_project_frames(ctypes.byref(p.c()), _ptr(frames), _ptr(evecs), _ptr(image), _ptr(workspace),
+                                   workspace.numel() * workspace.element_size(), _stream(stream)))
     return image
 
 

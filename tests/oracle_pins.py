@@ -316,4 +316,43 @@ def pin_fourier(o):
     return fails
 
 
-ALL_PINS = (pin_fresnel, pin_covariance, pin_eigh, pin_project, pin_fourier)
+def pin_first(o):
+    """The projection-first reformulation against the paper's order of steps."""
+    fails = []
+    rng = np.random.default_rng(16)
+    frames = _rand_frames(rng, 6, 8, 16)
+    nt, ny, nx = frames.shape
+    H = o.fresnel_ref(frames, LAM, Z, PITCH)
+    # 1. covariance from the frames = Eq. (4) on the holograms (Parseval, unit chirp)
+    Cf = o.covariance_frames_ref(frames)
+    e = _rel(Cf, o.covariance_ref(H))
+    _check(fails, "frame covariance = H^H H", e <= 1e-12, f"{e:.2e}")
+    # 2. integer brute force of one entry
+    s = sum(int(a) * int(b) for a, b in zip(frames[1].ravel(), frames[4].ravel())) * ny * nx
+    _check(fails, "frame covariance entry (1, 4) exact", Cf[1, 4] == s and Cf[4, 1] == s, f"{Cf[1, 4]} vs {s}")
+    # 3. image from combined frames = Eq. (6)-(7) on the holograms, for the
+    #    covariance's eigenvectors and for a random complex unitary V
+    lam, V = o.eigh_ref(Cf)
+    for name, W in (("eigenvectors", V),
+                    ("random unitary", np.linalg.qr(rng.standard_normal((nt, nt))
+                                                    + 1j * rng.standard_normal((nt, nt)))[0])):
+        for a, b in ((2, nt - 1), (0, 0), (1, 3)):
+            e = _rel(o.project_first_ref(frames, W, LAM, Z, PITCH, a, b), o.project_render_ref(H, W, a, b))
+            _check(fails, f"projection first = Eq. (6)-(7) ({name}, {a}..{b})", e <= 1e-10, f"{e:.2e}")
+    # 4. Parseval on the combined frames: sum_p M = N_pix sum_k ||J_k||^2
+    Vk = V[:, 2:nt]
+    J = Vk.T @ frames.reshape(nt, -1).astype(np.float64)
+    M = o.project_first_ref(frames, V, LAM, Z, PITCH, 2, nt - 1)
+    e = abs(M.sum() - ny * nx * np.sum(np.abs(J) ** 2)) / M.sum()
+    _check(fails, "sum M = N_pix sum ||J_k||^2", e <= 1e-10, f"{e:.2e}")
+    # 5. a real symmetric C has real phase-fixed eigenvectors (used by the GPU path)
+    _check(fails, "real eigenvectors", np.abs(V.imag).max() <= 1e-12, f"{np.abs(V.imag).max():.2e}")
+    # 6. the path end to end equals the paper's order of steps
+    r1 = o.pipeline_first_ref(frames, LAM, Z, PITCH, 2, nt - 1)
+    r0 = o.pipeline_ref(frames, LAM, Z, PITCH, 2, nt - 1)
+    e = _rel(r1["image"], r0["image"])
+    _check(fails, "projection-first pipeline = pipeline", e <= 1e-9, f"{e:.2e}")
+    return fails
+
+
+ALL_PINS = (pin_fresnel, pin_covariance, pin_eigh, pin_project, pin_fourier, pin_first)

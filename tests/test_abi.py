@@ -143,6 +143,41 @@ def test_precision_form_validation():
                            1, None) == hh.HH_E_INVALID
 
 
+def test_projection_first_validation():
+    L = hh.lib()
+    v16, v256 = ctypes.c_void_p(16), ctypes.c_void_p(256)
+    # projection first needs the exact form (C from the frames) ...
+    p = hh.Params(nx=64, ny=64, nt=8, k_lo=2, k_hi=7, proj_mode=hh.HH_PROJ_FIRST).c()
+    assert L.hh_pipeline(ctypes.byref(p), v256, v16, None, None, None, v256, 1 << 30, None) == hh.HH_E_INVALID
+    # ... and an entry point that starts from frames
+    for prec in (hh.HH_FP32, hh.HH_EXACT):
+        p = hh.Params(nx=64, ny=64, nt=8, k_lo=2, k_hi=7, precision=prec, proj_mode=hh.HH_PROJ_FIRST).c()
+        assert L.hh_project_render(ctypes.byref(p), v16, v16, v16, None) == hh.HH_E_UNSUPPORTED
+        assert L.hh_svd_filter(ctypes.byref(p), v16, v16, v16, None) == hh.HH_E_UNSUPPORTED
+        assert L.hh_fourier_render(ctypes.byref(p), v16, v16, None) == hh.HH_E_UNSUPPORTED
+    p = hh.Params(nx=64, ny=64, nt=8, k_lo=2, k_hi=7, precision=hh.HH_EXACT, proj_mode=hh.HH_PROJ_FIRST).c()
+    assert L.hh_pipeline(ctypes.byref(p), v256, v16, None, None, None, v256, 1, None) == hh.HH_E_WORKSPACE
+    p.proj_mode = 4
+    assert L.hh_pipeline(ctypes.byref(p), v256, v16, None, None, None, v256, 1 << 30, None) == hh.HH_E_INVALID
+    # the pipeline workspace adds the partial images to the exact form's
+    a = hh.workspace_bytes(hh.Params(nx=1024, ny=1024, nt=32, k_lo=2, k_hi=31, precision=hh.HH_EXACT))
+    b = hh.workspace_bytes(hh.Params(nx=1024, ny=1024, nt=32, k_lo=2, k_hi=31, precision=hh.HH_EXACT,
+                                     proj_mode=hh.HH_PROJ_FIRST))
+    assert b == a + 8 * 1024 * 1024 * 4
+    # hh_project_frames: K components and the partial images; alignment and size checks before device work
+    q = hh.Params(nx=128, ny=64, nt=16, k_lo=3, k_hi=12)
+    assert hh.project_frames_workspace_bytes(q) == 10 * 128 * 64 * 8 + 8 * 128 * 64 * 4
+    qc = q.c()
+    need = hh.project_frames_workspace_bytes(q)
+    assert L.hh_project_frames(ctypes.byref(qc), ctypes.c_void_p(8), v16, v16, v256, need, None) == hh.HH_E_INVALID
+    assert L.hh_project_frames(ctypes.byref(qc), v16, v16, v16, v256, need - 1, None) == hh.HH_E_WORKSPACE
+    assert L.hh_project_frames(ctypes.byref(qc), v16, v16, v16, ctypes.c_void_p(64), need, None) == \
+        hh.HH_E_WORKSPACE
+    assert L.hh_project_frames(ctypes.byref(qc), None, v16, v16, v256, need, None) == hh.HH_E_INVALID
+    bad = hh.Params(nx=128, ny=64, nt=16, k_lo=13, k_hi=12).c()
+    assert L.hh_project_frames_workspace_bytes(ctypes.byref(bad)) == 0
+
+
 def test_eigh_validation():
     L = hh.lib()
     v = ctypes.c_void_p(256)

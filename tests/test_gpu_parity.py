@@ -307,3 +307,23 @@ def test_pipeline_batch_repeated_launch(hh):
     b.run()
     for a, x in zip(first, imgs):
         assert np.array_equal(a, to_np(x))
+
+
+def test_fresnel_largest_frames(hh):
+    # the largest supported transform in both directions: 4096 x 4096 frames
+    import torch
+    f = _frames(4096, 2, 4096, 4096)
+    p = hh.Params(nx=4096, ny=4096, nt=2, k_lo=0, k_hi=1)
+    H = torch.empty((2, 4096, 4096), dtype=torch.complex64, device="cuda")
+    hh.hh_fresnel(p, to_dev(f), H)
+    got = to_np(H)
+    ref = oracle.fresnel_ref(f, LAM, Z, PITCH)
+    for t in range(2):
+        e = rel(got[t], ref[t])
+        say(f"fresnel 4096x4096 frame {t}: {e:.2e}")
+        assert e <= H_TOL
+
+
+def test_pipeline_longest_stack_paper_frames(hh):
+    # the longest supported stack (64 frames) at 1024 x 1024
+    _pipeline_check(hh, gen_stack(64, 64, 1024, 1024), 2, 63)

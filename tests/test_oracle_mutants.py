@@ -132,7 +132,46 @@ def fourier_with(W):
     return f
 
 
+def first_conjV(f, V, lam, z, d, a, b):
+    return _first_ok(f, np.conj(V), lam, z, d, a, b)
+
+
+def first_VT(f, V, lam, z, d, a, b):
+    return _first_ok(f, np.asarray(V).T, lam, z, d, a, b)
+
+
+def first_no_chirp(f, V, lam, z, d, a, b):
+    x = np.asarray(f)
+    nt, ny, nx = x.shape
+    J = (np.asarray(V)[:, a:b + 1].T @ x.reshape(nt, -1).astype(np.complex128)).reshape(-1, ny, nx)
+    return np.sum(np.abs(np.fft.fft2(J, axes=(-2, -1))) ** 2, axis=0)
+
+
+def first_exclusive(f, V, lam, z, d, a, b):
+    return _first_ok(f, V, lam, z, d, a, b - 1) if b > a else np.zeros(np.asarray(f).shape[1:])
+
+
+def _first_ok(*args):
+    return oracle.project_first_ref(*args)
+
+
+def covf_no_scale(f):
+    return oracle.covariance_frames_ref(f) / (f.shape[1] * f.shape[2])
+
+
+def covf_centred(f):
+    x = np.asarray(f).reshape(f.shape[0], -1).astype(np.float64)
+    x = x - x.mean(axis=0, keepdims=True)
+    return ((x @ x.T) * (f.shape[1] * f.shape[2])).astype(np.complex128)
+
+
 MUTANTS = {
+    "projection first on conj(V)": dict(project_first_ref=first_conjV),
+    "projection first on V^T": dict(project_first_ref=first_VT),
+    "projection first without chirp": dict(project_first_ref=first_no_chirp),
+    "projection first exclusive upper index": dict(project_first_ref=first_exclusive),
+    "frame covariance without N_pix": dict(covariance_frames_ref=covf_no_scale),
+    "centred frame covariance": dict(covariance_frames_ref=covf_centred),
     "conjugate chirp": dict(fresnel_ref=_fres(m_conj_chirp)),
     "inverse DFT": dict(fresnel_ref=_fres(m_inverse_dft)),
     "chirp origin at corner": dict(fresnel_ref=_fres(m_corner_origin)),

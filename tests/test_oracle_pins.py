@@ -3,7 +3,7 @@ import numpy as np
 import pytest
 
 import oracle
-from oracle_pins import pin_covariance, pin_eigh, pin_fourier, pin_fresnel, pin_project
+from oracle_pins import pin_covariance, pin_eigh, pin_first, pin_fourier, pin_fresnel, pin_project
 from paper_2004_00923_amd.synth import gen_stack
 
 
@@ -25,6 +25,10 @@ def test_pin_project_random():
 
 def test_pin_fourier():
     assert pin_fourier(oracle) == []
+
+
+def test_pin_projection_first():
+    assert pin_first(oracle) == []
 
 
 @pytest.fixture(scope="module")
