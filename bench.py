@@ -55,6 +55,21 @@ KERNEL_BYTES = {
 }
 
 
+K_KEPT = K_HI - K_LO + 1
+# Partial images of the projection-first column pass at 1024^2 on 256 compute units
+# (64 strips of 16 columns, about two groups per unit: 8 chunks of the kept list).
+ENERGY_CHUNKS = 8
+# Projection first (HH_PROJ_FIRST): the row pass reads the frames and writes the K
+# row-transformed combined frames (8 B per pixel each); the column pass reads them
+# and writes one partial image per chunk; the final sum reads the partials and
+# writes the image.
+KERNEL_BYTES.update({
+    "proj_rows": (2.0, 8.0 * K_KEPT),
+    "cols_energy": (0.0, 8.0 * K_KEPT + 4.0 * ENERGY_CHUNKS),
+    "energy_sum": (0.0, 4.0 * ENERGY_CHUNKS + 4.0),
+})
+
+
 def algorithmic_bytes(kernel: str, launches_per_step: int) -> float:
     """Compulsory HBM bytes of one launch of `kernel` for the 1024^2 x 32 stack;
     launches that split a stack (frame groups) share its bytes evenly."""
@@ -103,13 +118,19 @@ def measured_traffic(precision: str, tuning: str, kernel: str):
     return t["bytes"].get(kernel)
 
 
-def stack_bytes(precision: str) -> int:
+def stack_bytes(precision: str, proj: str = "auto") -> int:
     """Compulsory HBM bytes of one stack through the whole path: input once, the
     hologram written once and read by the covariance and by the projection, the
     image once (the row-to-column FFT intermediate is not counted).  The FP16
     storage form reads the input twice (mean, then transform), stores the residual
-    in 4 bytes and the complex64 mean once (written, read twice)."""
+    in 4 bytes and the complex64 mean once (written, read twice).  Projection
+    first forms no hologram: the input is read twice (covariance, row pass) and
+    the K row-transformed combined frames are written and read once (counted
+    here, as they are the only hologram-sized traffic of that form), plus the
+    partial images."""
     npf, npx = NT * NY * NX, NY * NX
+    if proj == "first":
+        return npf * (2 + 2) + npx * (2 * 8 * K_KEPT + 2 * 4 * ENERGY_CHUNKS + 4)
     if precision == "fp16store":
         return npf * (2 + 2 + 3 * 4) + npx * (4 + 4 + 3 * 8 + 4)
     if precision == "exact":   # covariance from the frames: input read twice, hologram written and read once
@@ -152,6 +173,9 @@ def main():
                     help="stacks per step, processed by one hh_pipeline_batch call (1 = hh_pipeline)")
     ap.add_argument("--precision", default="fp32",
                     help="arithmetic of the covariance contraction: fp32, bf16, fp16, bf16x3, fp16x3, fp8e4m3")
+    ap.add_argument("--proj", default="auto", choices=["auto", "direct", "complement", "first"],
+                    help="evaluation of the image: first = projection first from the frames (needs --precision "
+                         "exact)")
     ap.add_argument("--streams", type=int, default=4,
                     help="consecutive batches alternate over this many streams, each with its own workspace "
                          "and images (one batch's latency-bound eigensolver overlaps the next batch's FFTs)")
@@ -196,7 +220,9 @@ def main():
     if args.precision not in hh.PRECISIONS:
         print(f"bench.py: unknown --precision {args.precision}; one of {sorted(hh.PRECISIONS)}", file=sys.stderr)
         sys.exit(2)
-    p = hh.Params(nx=NX, ny=NY, nt=NT, k_lo=K_LO, k_hi=K_HI, precision=hh.PRECISIONS[args.precision])
+    p = hh.Params(nx=NX, ny=NY, nt=NT, k_lo=K_LO, k_hi=K_HI, precision=hh.PRECISIONS[args.precision],
+                  proj_mode=hh.PROJ_MODES[args.proj])
+    form = args.precision + ("+first" if args.proj == "first" else "")
     B = max(1, args.batch)
     ws1 = hh.alloc_workspace(hh.workspace_bytes(p), dev)
     if args.autotune:
@@ -277,7 +303,7 @@ def main():
     dom = max(kernels, key=lambda k: kernels[k]["avg_us"] * kernels[k]["launches_per_step"])
     d = kernels[dom]
     achieved = d["gbs"]
-    traffic = measured_traffic(args.precision, tuning_str, dom)
+    traffic = measured_traffic(form, tuning_str, dom)
     roofline = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
                 "traffic": traffic,
@@ -298,7 +324,7 @@ def main():
         lat.append(e0.elapsed_time(e1))
     lat = np.array(lat[10:])
 
-    sb = stack_bytes(args.precision)
+    sb = stack_bytes(args.precision, args.proj)
     out = {
         "metric": METRIC,
         "value": value,
@@ -313,8 +339,9 @@ def main():
         "dtype": "f32" if args.precision == "fp32" else f"f32 ({args.precision} covariance operands)",
         "data": "synthetic",
         "config": {"workload": "one 32x1024x1024 uint16 stack per step (4 seeded stacks rotated), "
-                               f"lambda 785 nm, pitch 20 um, z 0.3 m, PCs 2..31, {args.precision}",
-                   "stacks_per_s": value / NT, "precision": args.precision, "jacobi_sweeps": sweeps,
+                               f"lambda 785 nm, pitch 20 um, z 0.3 m, PCs 2..31, {form}",
+                   "stacks_per_s": value / NT, "precision": args.precision, "proj": args.proj,
+                   "jacobi_sweeps": sweeps,
                    "stacks_per_step": B, "ms_per_stack": ms_per_step / B, "tuning": tuning,
                    "streams": S},
         "roofline": roofline,

@@ -24,6 +24,16 @@ namespace {
 
 constexpr int kPfThreads = 256;
 
+// eight uint16 pixels (one 16-byte load) as floats, exact
+__device__ __forceinline__ void u16x8(const uint4 q, float (&x)[8]) {
+  const unsigned w[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    x[2 * i] = (float)(w[i] & 0xffffu);
+    x[2 * i + 1] = (float)(w[i] >> 16);
+  }
+}
+
 struct PfRowSlot {
   __device__ __forceinline__ int operator()(int e) const { return fft_pad(e); }
 };
@@ -60,7 +70,7 @@ __global__ __launch_bounds__(kPfThreads) void proj_rows(const uint16_t *__restri
   constexpr int E = C::E, T = C::T, KP = C::KP, KPAD = C::KPAD, LDSN = C::LDSN;
   typedef typename std::conditional<CPLX, float2, float>::type Coef;
   __shared__ __align__(16) float2 jb[C::LROWS * LDSN];
-  __shared__ __align__(16) Coef coef[64 * KPAD];  // coef[t][kk] = V[t][k] (t < nt)
+  __shared__ __align__(16) Coef coef[72 * KPAD];  // coef[t][kk] = V[t][k] (t < nt), zero for t >= nt
   __shared__ Coef ssum[KPAD];                     // s_k = sum_t V[t][k]
 
   const int g = blockIdx.x % groups, y = blockIdx.x / groups;
@@ -68,9 +78,9 @@ __global__ __launch_bounds__(kPfThreads) void proj_rows(const uint16_t *__restri
   const int kn = (K - kb) < KP ? (K - kb) : KP;       // components in this group
   const int tid = threadIdx.x;
 
-  for (int i = tid; i < nt * KPAD; i += kPfThreads) {
+  for (int i = tid; i < 72 * KPAD; i += kPfThreads) {  // rows t >= nt are zero (batches of 8 reach t < 72)
     const int t = i / KPAD, kk = i % KPAD;
-    const double2 v = kk < kn ? V[(size_t)t * nt + k_lo + kb + kk] : make_double2(0.0, 0.0);
+    const double2 v = (t < nt && kk < kn) ? V[(size_t)t * nt + k_lo + kb + kk] : make_double2(0.0, 0.0);
     if constexpr (CPLX) coef[i] = make_float2((float)v.x, (float)v.y);
     else coef[i] = (float)v.x;
   }
@@ -94,39 +104,50 @@ __global__ __launch_bounds__(kPfThreads) void proj_rows(const uint16_t *__restri
   const uint16_t *row0 = frames + (size_t)y * N;
   for (int item = tid; item < NCH * (KPAD / 4); item += kPfThreads) {
     const int c = item % NCH, q = item / NCH;
-    union U8 {
-      uint4 v;
-      uint16_t h[8];
-    };
-    U8 a0;
-    a0.v = reinterpret_cast<const uint4 *>(row0)[c];
+    const uint4 a0 = reinterpret_cast<const uint4 *>(row0)[c];
     float i0[8];
-#pragma unroll
-    for (int e = 0; e < 8; ++e) i0[e] = (float)a0.h[e];
+    u16x8(a0, i0);
     float jr[4][8], ji[4][8];
 #pragma unroll
     for (int kk = 0; kk < 4; ++kk)
 #pragma unroll
       for (int e = 0; e < 8; ++e) jr[kk][e] = ji[kk][e] = 0.0f;
-    for (int t = 1; t < nt; ++t) {
-      U8 a;
-      a.v = reinterpret_cast<const uint4 *>(row0 + (size_t)t * fstride)[c];
-      float d[8];
+    // frames in batches of eight, the next batch's loads in flight while the
+    // current one is summed; slots beyond nt reload the last frame and meet zero
+    // coefficients
+    auto load8 = [&](int t0, uint4 (&a)[8]) {
 #pragma unroll
-      for (int e = 0; e < 8; ++e) d[e] = (float)a.h[e] - i0[e];  // exact: integers below 2^17
+      for (int j = 0; j < 8; ++j) {
+        const int tt = (t0 + j < nt) ? t0 + j : nt - 1;
+        a[j] = reinterpret_cast<const uint4 *>(row0 + (size_t)tt * fstride)[c];
+      }
+    };
+    uint4 a[8], nx8[8];
+    load8(1, a);
+    for (int t0 = 1; t0 < nt; t0 += 8) {
+      if (t0 + 8 < nt) load8(t0 + 8, nx8);
 #pragma unroll
-      for (int kk = 0; kk < 4; ++kk) {
-        const Coef v = coef[t * KPAD + 4 * q + kk];
+      for (int j = 0; j < 8; ++j) {
+        float d[8];
+        u16x8(a[j], d);
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
-          if constexpr (CPLX) {
-            jr[kk][e] = fmaf(v.x, d[e], jr[kk][e]);
-            ji[kk][e] = fmaf(v.y, d[e], ji[kk][e]);
-          } else {
-            jr[kk][e] = fmaf(v, d[e], jr[kk][e]);
+        for (int e = 0; e < 8; ++e) d[e] -= i0[e];  // exact: integers below 2^17
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) {
+          const Coef v = coef[(t0 + j) * KPAD + 4 * q + kk];
+#pragma unroll
+          for (int e = 0; e < 8; ++e) {
+            if constexpr (CPLX) {
+              jr[kk][e] = fmaf(v.x, d[e], jr[kk][e]);
+              ji[kk][e] = fmaf(v.y, d[e], ji[kk][e]);
+            } else {
+              jr[kk][e] = fmaf(v, d[e], jr[kk][e]);
+            }
           }
         }
       }
+#pragma unroll
+      for (int j = 0; j < 8; ++j) a[j] = nx8[j];
     }
 #pragma unroll
     for (int kk = 0; kk < 4; ++kk) {
