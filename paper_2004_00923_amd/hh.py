@@ -441,7 +441,11 @@ def profile_reset():
 
 def profile_read() -> dict:
     import json
-    n = lib().hh_profile_read(None, 0)
-    buf = ctypes.create_string_buffer(n)
-    lib().hh_profile_read(buf, n)
+    size = 1 << 16
+    while True:  # one formatting per read: the buffer is grown until the text fits whole
+        buf = ctypes.create_string_buffer(size)
+        n = lib().hh_profile_read(buf, size)
+        if n <= size:
+            break
+        size = n + 4096
     return {k: (int(v[0]), float(v[1])) for k, v in json.loads(buf.value.decode()).items()}
