@@ -73,7 +73,11 @@ __global__ __launch_bounds__(kPfThreads) void proj_rows(const uint16_t *__restri
   __shared__ __align__(16) Coef coef[72 * KPAD];  // coef[t][kk] = V[t][k] (t < nt), zero for t >= nt
   __shared__ Coef ssum[KPAD];                     // s_k = sum_t V[t][k]
 
-  const int g = blockIdx.x % groups, y = blockIdx.x / groups;
+  // XCD-aware order: workgroups go round-robin to the 8 XCDs, so the groups of one
+  // row are given to blocks b, b + 8, b + 16, ... (one XCD, one L2), which read
+  // the row's frames once from memory and then from that L2
+  const int xcd = blockIdx.x & 7, slot = blockIdx.x >> 3;
+  const int g = slot % groups, y = (slot / groups) * 8 + xcd;
   const int kb = g * KP;                              // first kept component of this group (0-based in the list)
   const int kn = (K - kb) < KP ? (K - kb) : KP;       // components in this group
   const int tid = threadIdx.x;
