@@ -56,16 +56,14 @@ __device__ __forceinline__ double rcp64(double x) {
   return y;
 }
 
-// Per-round rotation data, indexed by matrix index i: partner, c_i, e_i = J[partner][i],
-// the new diagonal if rotated, and the pair list.
+// Per-round rotation data, indexed by matrix index i: whether i's pair rotates, c_i,
+// e_i = J[partner][i] and the new diagonal (the pairs are recomputed by pair_of).
 template <int NMAX>
 struct RoundParams {
-  int part[NMAX];
   int rot[NMAX];
   double c[NMAX];
   double2 e[NMAX];
   double d[NMAX];
-  int pl[NMAX / 2], ql[NMAX / 2];
 };
 
 // Round-robin pairing: pair k of round r among m players (p < q; q may be the dummy).
@@ -73,9 +71,9 @@ __device__ __forceinline__ void pair_of(int r, int k, int m, int &p, int &q) {
   if (k == 0) {
     p = r;
     q = m - 1;
-  } else {
-    p = (r + k) % (m - 1);
-    q = (r - k + m - 1) % (m - 1);
+  } else {  // (r + k) mod (m - 1) and (r - k) mod (m - 1), with 0 <= r < m - 1, 0 < k < m / 2
+    p = r + k >= m - 1 ? r + k - (m - 1) : r + k;
+    q = r - k < 0 ? r - k + (m - 1) : r - k;
   }
   if (p > q) {
     const int x = p;
@@ -87,17 +85,12 @@ __device__ __forceinline__ void pair_of(int r, int k, int m, int &p, int &q) {
 template <int NMAX>
 __device__ __forceinline__ void set_rotation(RoundParams<NMAX> &P, int k, int p, int q, int n, double a, double b,
                                              double2 beta, double abs2) {
-  P.pl[k] = p;
-  P.ql[k] = q;
   if (q >= n) {  // paired with the dummy index: no rotation
-    P.part[p] = p;
     P.rot[p] = 0;
     P.c[p] = 1.0;
     P.e[p] = make_double2(0.0, 0.0);
     return;
   }
-  P.part[p] = q;
-  P.part[q] = p;
   const double ab2 = beta.x * beta.x + beta.y * beta.y;
   if (ab2 > kRelTol * kRelTol * fabs(a * b) && ab2 > abs2) {
     const double g = b - a, ag = fabs(g), sg = g >= 0.0 ? 1.0 : -1.0;
@@ -123,21 +116,6 @@ __device__ __forceinline__ void set_rotation(RoundParams<NMAX> &P, int k, int p,
     P.rot[p] = 0;
     P.rot[q] = 0;
   }
-}
-
-// One entry of J^H A J (A given by row stride ld) under the rotations in P.
-template <int NMAX>
-__device__ __forceinline__ double2 rotated_entry(const double2 *A, int ld, const RoundParams<NMAX> &P, int i, int j) {
-  const int ip = P.part[i], jp = P.part[j];
-  if (i == j) return make_double2(P.rot[i] ? P.d[i] : A[i * ld + i].x, 0.0);
-  if (j == ip && P.rot[i]) return make_double2(0.0, 0.0);
-  const double ci = P.c[i], cj = P.c[j];
-  const double2 eic = zconj(P.e[i]), ej = P.e[j];
-  double2 x = zscale(A[i * ld + j], ci * cj);
-  x = zadd(x, zmul(zscale(ej, ci), A[i * ld + jp]));
-  x = zadd(x, zmul(zscale(eic, cj), A[ip * ld + j]));
-  x = zadd(x, zmul(zmul(eic, ej), A[ip * ld + jp]));
-  return x;
 }
 
 // C into A (scaled by an exact power of two so that its Frobenius norm is O(1))
@@ -303,6 +281,16 @@ __global__ __launch_bounds__(threads_for<NMAX>()) void eigh_jacobi(EighBatch bat
     }
   }
 
+  // V items (row, pair) of this thread (waves 1..), fixed for every round
+  int vRow[VPT], vK[VPT];
+#pragma unroll
+  for (int u = 0; u < VPT; ++u) {
+    const int it = (tid - 64) + VTH * u;
+    const bool ok = tid >= 64 && it < n * np;
+    vRow[u] = ok ? it / np : -1;
+    vK[u] = ok ? it - (it / np) * np : 0;
+  }
+
   const double scale = load_scaled<NMAX, kThreads>(pr, A, V, red);
   const double fro = red[0] / scale;  // Frobenius norm of C (exactly, scale is a power of two)
   const double abs2 = (kAbsTol * fro * scale) * (kAbsTol * fro * scale);
@@ -344,14 +332,19 @@ __global__ __launch_bounds__(threads_for<NMAX>()) void eigh_jacobi(EighBatch bat
 #pragma unroll
       for (int u = 0; u < BPT; ++u) {
         if (bP[u] < 0) continue;
-        const int p1 = P.pl[bP[u]], q1 = P.ql[bP[u]], p2 = P.pl[bQ[u]], q2 = P.ql[bQ[u]];
+        // the pairing is fixed arithmetic: recomputed in registers (no dependent LDS read)
+        int p1, q1, p2, q2;
+        pair_of(r, bP[u], m, p1, q1);
+        pair_of(r, bQ[u], m, p2, q2);
         if (bP[u] == bQ[u]) {
           if (q1 < n) {
-            const double2 x = rotated_entry(A, LD, P, p1, q1);
-            const double2 dp = rotated_entry(A, LD, P, p1, p1);
-            const double2 dq = rotated_entry(A, LD, P, q1, q1);
-            A[p1 * LD + p1] = dp;
-            A[q1 * LD + q1] = dq;
+            // the pair's own 2x2 block: zeroed off-diagonal and moved diagonal if rotated
+            const bool rot = P.rot[p1] != 0;
+            const double dp = rot ? P.d[p1] : A[p1 * LD + p1].x;
+            const double dq = rot ? P.d[q1] : A[q1 * LD + q1].x;
+            const double2 x = rot ? make_double2(0.0, 0.0) : A[p1 * LD + q1];
+            A[p1 * LD + p1] = make_double2(dp, 0.0);
+            A[q1 * LD + q1] = make_double2(dq, 0.0);
             A[p1 * LD + q1] = x;
             A[q1 * LD + p1] = zconj(x);
           }
@@ -405,10 +398,10 @@ __global__ __launch_bounds__(threads_for<NMAX>()) void eigh_jacobi(EighBatch bat
         // (2b) waves 1..3: V <- V J, one (row, pair) item at a time, in place
 #pragma unroll
         for (int u = 0; u < VPT; ++u) {
-          const int it = (tid - 64) + VTH * u;
-          if (it < n * np) {
-            const int row = it / np, k = it - (it / np) * np;
-            const int p = P.pl[k], q = P.ql[k];
+          if (vRow[u] >= 0) {
+            const int row = vRow[u];
+            int p, q;
+            pair_of(r, vK[u], m, p, q);
             if (q < n && P.rot[p]) {
               const double2 vp = V[row * LD + p], vq = V[row * LD + q];
               const double c = P.c[p];
