@@ -27,6 +27,7 @@ namespace {
 typedef float v16f __attribute__((ext_vector_type(16)));
 typedef float v4f __attribute__((ext_vector_type(4)));
 typedef double v4d __attribute__((ext_vector_type(4)));
+typedef int v4i __attribute__((ext_vector_type(4)));
 
 // Output of accumulator register r on lane l of a 32x32 MFMA block.
 __device__ __forceinline__ int acc_row(int lane, int r) { return 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3); }
@@ -686,6 +687,145 @@ __global__ __launch_bounds__(256) void gram_partial_r16(const h2 *__restrict__ R
 }
 
 
+// The same exact Gram on integer MFMA (n_t <= 32).  Each 16-bit value is written
+// with two signed 8-bit digits around the offset o = 32896 = 128 * 257:
+//   x = 256 h + l + o,   h = (x >> 8) - 128,   l = (x & 255) - 128   (both in [-128, 127]),
+// so that, summed over the pixels of a chunk (P of them),
+//   sum x_s x_t = 2^16 (h^T h) + 2^8 (h^T l + l^T h) + (l^T l) + o (S_s + S_t) + P o^2,
+// with S_s = sum (x_s - o).  Pixels past the end load as x = 0 and drop out of the
+// identity exactly.  h^T h and l^T l (blocks a <= b) and h^T l (all blocks) run on
+// v_mfma_i32_16x16x64_i8; every int32 sum stays below 2^31 (at most pxw products of
+// magnitude <= 2^14 each), and the combination in FP64 is exact (integers below
+// 2^53), so the result equals the FP64 kernel's bit for bit.  As bytes, l and h are
+// the low and high bytes of x with the top bit flipped.  Lane (f, kq) holds frames
+// f + 16 b of the 16 pixels 16 kq .. 16 kq + 15 of each 64-pixel step (two 16-byte
+// loads per frame); the 32-bit 16x16 accumulator layout puts row 4 kq + r, column f
+// in register r of lane (f, kq).
+template <int NB>
+__global__ __launch_bounds__(256) void gram_partial_u16_i8(const uint16_t *__restrict__ I, int nt, long long npix,
+                                                            int pxw, double npix_d, double *__restrict__ partial) {
+  static_assert(NB == 1 || NB == 2, "integer form for n_t <= 32");
+  constexpr int D = 32;
+  constexpr int NSYM = NB * (NB + 1) / 2, NCROSS = NB * NB;
+  constexpr double kOff = 32896.0;
+  __shared__ double red[D * D];
+  __shared__ double ssum[D];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int f = lane & 15, kq = lane >> 4;
+  const long long p0 = ((long long)blockIdx.x * 4 + wave) * pxw;
+  const uint4 *src[NB];
+  bool valid[NB];
+#pragma unroll
+  for (int b = 0; b < NB; ++b) {
+    valid[b] = 16 * b + f < nt;
+    src[b] = reinterpret_cast<const uint4 *>(I + (long long)(valid[b] ? 16 * b + f : 0) * npix + p0) + 2 * kq;
+  }
+  v4i hh[NSYM], ll[NSYM], hl[NCROSS];
+#pragma unroll
+  for (int q = 0; q < NSYM; ++q) hh[q] = ll[q] = v4i{0, 0, 0, 0};
+#pragma unroll
+  for (int q = 0; q < NCROSS; ++q) hl[q] = v4i{0, 0, 0, 0};
+  int xsum[NB];  // sum of this lane's raw values per frame block
+#pragma unroll
+  for (int b = 0; b < NB; ++b) xsum[b] = 0;
+  const int steps = pxw / 64;
+  for (int j = 0; j < steps; ++j) {
+    const bool in = p0 + 64 * j + 16 * kq < npix;  // npix is a multiple of 64
+    v4i H[NB], L[NB];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      uint4 w[2];
+      w[0] = (valid[b] && in) ? src[b][8 * j] : make_uint4(0u, 0u, 0u, 0u);
+      w[1] = (valid[b] && in) ? src[b][8 * j + 1] : make_uint4(0u, 0u, 0u, 0u);
+      const unsigned u[8] = {w[0].x, w[0].y, w[0].z, w[0].w, w[1].x, w[1].y, w[1].z, w[1].w};
+      int h4[4], l4[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        // bytes of u[2q], u[2q+1]: lo0 hi0 lo1 hi1 | lo2 hi2 lo3 hi3, top bits flipped
+        const unsigned a = u[2 * q] ^ 0x80808080u, c = u[2 * q + 1] ^ 0x80808080u;
+        l4[q] = (int)__builtin_amdgcn_perm(c, a, 0x06040200u);  // lo0 lo1 lo2 lo3
+        h4[q] = (int)__builtin_amdgcn_perm(c, a, 0x07050301u);  // hi0 hi1 hi2 hi3
+        xsum[b] += (int)((u[2 * q] & 0xffffu) + (u[2 * q] >> 16) + (u[2 * q + 1] & 0xffffu) + (u[2 * q + 1] >> 16));
+      }
+      H[b] = v4i{h4[0], h4[1], h4[2], h4[3]};
+      L[b] = v4i{l4[0], l4[1], l4[2], l4[3]};
+    }
+    int q = 0;
+#pragma unroll
+    for (int a = 0; a < NB; ++a)
+#pragma unroll
+      for (int b = a; b < NB; ++b, ++q) {
+        hh[q] = __builtin_amdgcn_mfma_i32_16x16x64_i8(H[a], H[b], hh[q], 0, 0, 0);
+        ll[q] = __builtin_amdgcn_mfma_i32_16x16x64_i8(L[a], L[b], ll[q], 0, 0, 0);
+      }
+#pragma unroll
+    for (int a = 0; a < NB; ++a)
+#pragma unroll
+      for (int b = 0; b < NB; ++b)
+        hl[a * NB + b] = __builtin_amdgcn_mfma_i32_16x16x64_i8(H[a], L[b], hl[a * NB + b], 0, 0, 0);
+  }
+  // per-frame sums over the wave: the four lanes kq of frame f
+  double fs[NB];
+#pragma unroll
+  for (int b = 0; b < NB; ++b) {
+    int v = xsum[b];
+    v += __shfl_xor(v, 16);
+    v += __shfl_xor(v, 32);
+    fs[b] = (double)v;
+  }
+  // fixed-order combination of the four waves (exact: integer-valued doubles), then one store
+  for (int i = tid; i < D * D; i += 256) red[i] = 0.0;
+  if (tid < D) ssum[tid] = 0.0;
+  __syncthreads();
+#pragma unroll 1
+  for (int w = 0; w < 4; ++w) {
+    if (wave == w) {
+      int q = 0;
+#pragma unroll
+      for (int a = 0; a < NB; ++a)
+#pragma unroll
+        for (int b = a; b < NB; ++b, ++q)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int i = 16 * a + 4 * kq + r, jj = 16 * b + f;
+            const double v = 65536.0 * (double)hh[q][r] + (double)ll[q][r];
+            red[i * D + jj] += v;
+            if (a != b) red[jj * D + i] += v;
+          }
+      // h^T l counts at (i, j) and mirrored at (j, i): h^T l + l^T h
+#pragma unroll
+      for (int a = 0; a < NB; ++a)
+#pragma unroll
+        for (int b = 0; b < NB; ++b)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int i = 16 * a + 4 * kq + r, jj = 16 * b + f;
+            const double v = 256.0 * (double)hl[a * NB + b][r];
+            red[i * D + jj] += v;
+            red[jj * D + i] += v;
+          }
+      if (kq == 0) {
+#pragma unroll
+        for (int b = 0; b < NB; ++b) ssum[16 * b + f] += fs[b];
+      }
+    }
+    __syncthreads();
+  }
+  // + o (S_s + S_t) + P o^2 with S = (sum of x) - o P, P = the block's 4 pxw pixels
+  const double P = 4.0 * (double)pxw;
+  double *out = partial + (size_t)blockIdx.x * partial_len(D);
+  for (int i = tid; i < partial_len(D); i += 256) {
+    double v = 0.0;
+    if (i < D * D) {
+      const int s_ = i / D, t_ = i - (i / D) * D;
+      const double Ss = ssum[s_] - kOff * P, St = ssum[t_] - kOff * P;
+      v = (red[i] + kOff * (Ss + St) + P * kOff * kOff) * npix_d;
+    }
+    out[i] = v;
+  }
+}
+
 // Exact covariance from the frames (n_t <= 64): because the input chirp has unit
 // modulus and the unnormalised DFT satisfies F^H F = N_pix I, C = H^H H of Eq. (4)
 // equals N_pix I^T I for the real interferogram matrix I, an integer Gram.  Its
@@ -866,8 +1006,8 @@ hipError_t launch_gram_u16(const GramLayout &L, const uint16_t *frames, int nt, 
     ProfScope ps("gram_partial_u16", s);
     const dim3 g(L.groups), b(256);
     const double nd = (double)npix;
-    if (nt <= 16) hipLaunchKernelGGL(gram_partial_u16<1>, g, b, 0, s, frames, nt, npix, L.pxw, nd, partial);
-    else if (nt <= 32) hipLaunchKernelGGL(gram_partial_u16<2>, g, b, 0, s, frames, nt, npix, L.pxw, nd, partial);
+    if (nt <= 16) hipLaunchKernelGGL(gram_partial_u16_i8<1>, g, b, 0, s, frames, nt, npix, L.pxw, nd, partial);
+    else if (nt <= 32) hipLaunchKernelGGL(gram_partial_u16_i8<2>, g, b, 0, s, frames, nt, npix, L.pxw, nd, partial);
     else if (nt <= 48) hipLaunchKernelGGL(gram_partial_u16<3>, g, b, 0, s, frames, nt, npix, L.pxw, nd, partial);
     else hipLaunchKernelGGL(gram_partial_u16<4>, g, b, 0, s, frames, nt, npix, L.pxw, nd, partial);
   }
