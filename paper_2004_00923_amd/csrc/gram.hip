@@ -28,6 +28,7 @@ typedef float v16f __attribute__((ext_vector_type(16)));
 typedef float v4f __attribute__((ext_vector_type(4)));
 typedef double v4d __attribute__((ext_vector_type(4)));
 typedef int v4i __attribute__((ext_vector_type(4)));
+typedef float v16f __attribute__((ext_vector_type(16)));
 
 // Output of accumulator register r on lane l of a 32x32 MFMA block.
 __device__ __forceinline__ int acc_row(int lane, int r) { return 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3); }
@@ -80,24 +81,53 @@ __global__ __launch_bounds__(256) void gram_partial16(const float2 *__restrict__
 
   const long long p0 = ((long long)blockIdx.x * 4 + wave) * pxw;  // first pixel of this wave
   const bool v0 = f < nt, v1 = TWO && (16 + f) < nt;
-  const float4 *s0p = reinterpret_cast<const float4 *>(H + (long long)(v0 ? f : 0) * npix + p0) + k;
-  const float4 *s1p = reinterpret_cast<const float4 *>(H + (long long)(v1 ? 16 + f : 0) * npix + p0) + k;
-
+  const float4 *f0 = reinterpret_cast<const float4 *>(H + (long long)(v0 ? f : 0) * npix);
+  const float4 *f1 = reinterpret_cast<const float4 *>(H + (long long)(v1 ? 16 + f : 0) * npix);
+  // Loads are unconditional (past the end they read the frame's first pixels, and
+  // the prefetch after the last chunk reads that chunk again) and masked when the
+  // chunk is taken up, so the next chunk's loads stay in flight while the current
+  // one is summed.  A chunk is held in vector registers (16 floats per frame
+  // stream), which the compiler keeps out of scratch across iterations.
+  v16f h0, h1, n0, n1;
+  unsigned hmask = 0, nmask = 0;  // bit g: pixel pair g of the chunk is inside the frame
+#pragma unroll
+  for (int g = 0; g < G4; ++g) {
+    const long long px = p0 + 8 * g + 2 * k;
+    const bool in = px < npix;
+    hmask |= in ? (1u << g) : 0u;
+    const float4 a = f0[in ? (px >> 1) : 0], b = f1[in ? (px >> 1) : 0];
+    h0[4 * g] = a.x; h0[4 * g + 1] = a.y; h0[4 * g + 2] = a.z; h0[4 * g + 3] = a.w;
+    h1[4 * g] = b.x; h1[4 * g + 1] = b.y; h1[4 * g + 2] = b.z; h1[4 * g + 3] = b.w;
+  }
   for (int q0 = 0; q0 < pxw; q0 += 8 * G4) {
-    float4 h0[G4], h1[G4];
+    const int qn = (q0 + 8 * G4 < pxw) ? q0 + 8 * G4 : q0;
+    nmask = 0;
 #pragma unroll
     for (int g = 0; g < G4; ++g) {
-      const bool in = p0 + q0 + 8 * g + 2 * k < npix;
-      h0[g] = (v0 && in) ? s0p[(q0 >> 1) + 4 * g] : make_float4(0.f, 0.f, 0.f, 0.f);
-      h1[g] = (v1 && in) ? s1p[(q0 >> 1) + 4 * g] : make_float4(0.f, 0.f, 0.f, 0.f);
+      const long long px = p0 + qn + 8 * g + 2 * k;
+      const bool in = px < npix;
+      nmask |= in ? (1u << g) : 0u;
+      const float4 a = f0[in ? (px >> 1) : 0], b = f1[in ? (px >> 1) : 0];
+      n0[4 * g] = a.x; n0[4 * g + 1] = a.y; n0[4 * g + 2] = a.z; n0[4 * g + 3] = a.w;
+      n1[4 * g] = b.x; n1[4 * g + 1] = b.y; n1[4 * g + 2] = b.z; n1[4 * g + 3] = b.w;
+    }
+    float4 hc0[G4], hc1[G4];  // the current chunk, masked
+#pragma unroll
+    for (int g = 0; g < G4; ++g) {
+      const bool in = (hmask >> g) & 1u;
+      const bool i0 = v0 && in, i1 = v1 && in;
+      hc0[g] = make_float4(i0 ? h0[4 * g] : 0.f, i0 ? h0[4 * g + 1] : 0.f, i0 ? h0[4 * g + 2] : 0.f,
+                           i0 ? h0[4 * g + 3] : 0.f);
+      hc1[g] = make_float4(i1 ? h1[4 * g] : 0.f, i1 ? h1[4 * g + 1] : 0.f, i1 ? h1[4 * g + 2] : 0.f,
+                           i1 ? h1[4 * g + 3] : 0.f);
     }
     float a0r = 0.f, a0i = 0.f, a1r = 0.f, a1i = 0.f, mmf = 0.f;  // FP32 sums over 8 pixels per lane
 #pragma unroll
     for (int g = 0; g < G4; ++g) {
 #pragma unroll
       for (int e = 0; e < 2; ++e) {
-        float2 x0 = e ? make_float2(h0[g].z, h0[g].w) : make_float2(h0[g].x, h0[g].y);
-        float2 x1 = e ? make_float2(h1[g].z, h1[g].w) : make_float2(h1[g].x, h1[g].y);
+        float2 x0 = e ? make_float2(hc0[g].z, hc0[g].w) : make_float2(hc0[g].x, hc0[g].y);
+        float2 x1 = e ? make_float2(hc1[g].z, hc1[g].w) : make_float2(hc1[g].x, hc1[g].y);
         float mr, mi;
         if constexpr (MEAN) {
           mr = sum16(x0.x + x1.x) * inv_nt;
@@ -138,6 +168,9 @@ __global__ __launch_bounds__(256) void gram_partial16(const float2 *__restrict__
     a1.x += a1r;
     a1.y += a1i;
     mm += mmf;
+    h0 = n0;
+    h1 = n1;
+    hmask = nmask;
   }
 
   // fixed-order FP64 combination of the four waves, then one store
@@ -714,12 +747,12 @@ __global__ __launch_bounds__(256) void gram_partial_u16_i8(const uint16_t *__res
   const int lane = tid & 63, wave = tid >> 6;
   const int f = lane & 15, kq = lane >> 4;
   const long long p0 = ((long long)blockIdx.x * 4 + wave) * pxw;
-  const uint4 *src[NB];
+  const uint4 *src[NB];  // frame start (frame 0 for frames past nt)
   bool valid[NB];
 #pragma unroll
   for (int b = 0; b < NB; ++b) {
     valid[b] = 16 * b + f < nt;
-    src[b] = reinterpret_cast<const uint4 *>(I + (long long)(valid[b] ? 16 * b + f : 0) * npix + p0) + 2 * kq;
+    src[b] = reinterpret_cast<const uint4 *>(I + (long long)(valid[b] ? 16 * b + f : 0) * npix);
   }
   v4i hh[NSYM], ll[NSYM], hl[NCROSS];
 #pragma unroll
@@ -729,16 +762,36 @@ __global__ __launch_bounds__(256) void gram_partial_u16_i8(const uint16_t *__res
   int xsum[NB];  // sum of this lane's raw values per frame block
 #pragma unroll
   for (int b = 0; b < NB; ++b) xsum[b] = 0;
+  // Loads are unconditional (past the end they read the frame's first pixels; the
+  // prefetch after the last step repeats that step) and masked when the step is
+  // taken up, so the next step's loads stay in flight during the MFMAs; a step's
+  // raw words sit in vector registers (8 dwords per frame block).
+  typedef unsigned v8u __attribute__((ext_vector_type(8)));
   const int steps = pxw / 64;
+  v8u cur[NB], nxt[NB];
+  bool cin = p0 + 16 * kq < npix, nin = cin;  // npix is a multiple of 64
+#pragma unroll
+  for (int b = 0; b < NB; ++b) {
+    const long long idx = cin ? (p0 + 16 * kq) / 8 : 0;
+    const uint4 w0 = src[b][idx], w1 = src[b][idx + 1];
+    cur[b] = v8u{w0.x, w0.y, w0.z, w0.w, w1.x, w1.y, w1.z, w1.w};
+  }
   for (int j = 0; j < steps; ++j) {
-    const bool in = p0 + 64 * j + 16 * kq < npix;  // npix is a multiple of 64
+    const int jn = j + 1 < steps ? j + 1 : j;
+    nin = p0 + 64 * jn + 16 * kq < npix;
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      const long long idx = nin ? (p0 + 64 * jn + 16 * kq) / 8 : 0;
+      const uint4 w0 = src[b][idx], w1 = src[b][idx + 1];
+      nxt[b] = v8u{w0.x, w0.y, w0.z, w0.w, w1.x, w1.y, w1.z, w1.w};
+    }
     v4i H[NB], L[NB];
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
-      uint4 w[2];
-      w[0] = (valid[b] && in) ? src[b][8 * j] : make_uint4(0u, 0u, 0u, 0u);
-      w[1] = (valid[b] && in) ? src[b][8 * j + 1] : make_uint4(0u, 0u, 0u, 0u);
-      const unsigned u[8] = {w[0].x, w[0].y, w[0].z, w[0].w, w[1].x, w[1].y, w[1].z, w[1].w};
+      const bool ok = valid[b] && cin;
+      unsigned u[8];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) u[e] = ok ? cur[b][e] : 0u;
       int h4[4], l4[4];
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
@@ -764,6 +817,9 @@ __global__ __launch_bounds__(256) void gram_partial_u16_i8(const uint16_t *__res
 #pragma unroll
       for (int b = 0; b < NB; ++b)
         hl[a * NB + b] = __builtin_amdgcn_mfma_i32_16x16x64_i8(H[a], L[b], hl[a * NB + b], 0, 0, 0);
+#pragma unroll
+    for (int b = 0; b < NB; ++b) cur[b] = nxt[b];
+    cin = nin;
   }
   // per-frame sums over the wave: the four lanes kq of frame f
   double fs[NB];
