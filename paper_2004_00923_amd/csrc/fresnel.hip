@@ -209,7 +209,8 @@ __device__ __forceinline__ void row_load(RowIn<IN> (&in)[N / 8 / (N / fft_e(N, E
 #pragma unroll
   for (int l = 0; l < L; ++l) {
     const int c = t + T * l;
-    if (!live || c >= N / 8) continue;
+    (void)live;  // rows past the end load row 0 of frame 0 (a valid address) and are zeroed when staged
+    if (c >= N / 8) continue;
     if constexpr (IN == kInF32) {
       const float4 *s4 = reinterpret_cast<const float4 *>(static_cast<const float *>(src) + base) + 2 * c;
       in[l].a = s4[0];
@@ -240,6 +241,15 @@ __global__ __launch_bounds__(ROWS *(N / fft_e(N, EP))) void fresnel_rows_persist
   float2 cx[E];
 #pragma unroll
   for (int i = 0; i < E; ++i) cx[i] = chirp_x[t + T * i];
+  // The twiddles come from LDS (up to 2048 points): a global twiddle load issued
+  // after the next item's prefetch would make the transform wait for that prefetch.
+  constexpr bool kTwLds = N <= 2048;
+  __shared__ float2 tws[kTwLds ? N : 1];
+  if constexpr (kTwLds) {
+    for (int i = threadIdx.x; i < N; i += ROWS * T) tws[i] = tw[i];
+    __syncthreads();
+  }
+  const float2 *twp = kTwLds ? tws : tw;
   auto where = [&](int item, int &row, size_t &base, size_t &mbase) {
     const int f = item / groups;
     row = (item - f * groups) * ROWS + r;
@@ -248,17 +258,21 @@ __global__ __launch_bounds__(ROWS *(N / fft_e(N, EP))) void fresnel_rows_persist
     mbase = (size_t)(live ? row : 0) * N;
     return live;
   };
+  // The loads are unconditional (an item past the end loads row 0 of frame 0, a
+  // valid address): with no branch around the prefetch, the transform of the current
+  // item does not wait for the next item's loads.
   RowIn<IN> cur[L], nxt[L];
-  int item = blockIdx.x, row;
-  size_t base, mbase;
+  int item = blockIdx.x, row = 0;
+  size_t base = 0, mbase = 0;
   bool live = item < items && where(item, row, base, mbase);
-  if (item < items) row_load<N, EP, IN>(cur, src, mean, base, mbase, t, live);
+  row_load<N, EP, IN>(cur, src, mean, base, mbase, t, live);
   for (; item < items; item += gridDim.x) {
     const int item2 = item + gridDim.x;
-    int row2;
+    int row2 = 0;
     size_t base2 = 0, mbase2 = 0;
     const bool live2 = item2 < items && where(item2, row2, base2, mbase2);
-    if (item2 < items) row_load<N, EP, IN>(nxt, src, mean, base2, mbase2, t, live2);
+    const float2 cy = chirp_y[live ? row : 0];  // issued before the prefetch
+    row_load<N, EP, IN>(nxt, src, mean, base2, mbase2, t, live2);
 #pragma unroll
     for (int l = 0; l < L; ++l) {
       const int c = t + T * l;
@@ -286,7 +300,6 @@ __global__ __launch_bounds__(ROWS *(N / fft_e(N, EP))) void fresnel_rows_persist
       stage8<(FftCfg<N, EP>::LDSN * sizeof(Slot)) % 16 == 0>(stage + 8 * c, x);
     }
     __syncthreads();
-    const float2 cy = chirp_y[live ? row : 0];
     float2 v[E];
 #pragma unroll
     for (int i = 0; i < E; ++i) {
@@ -295,7 +308,7 @@ __global__ __launch_bounds__(ROWS *(N / fft_e(N, EP))) void fresnel_rows_persist
       v[i] = make_float2(val * c.x, val * c.y);
     }
     __syncthreads();
-    fft_passes<N, EP, 0, SPLIT>(v, t, tw, lds + r * FftCfg<N, EP>::LDSN, RowSlot{});
+    fft_passes<N, EP, 0, SPLIT>(v, t, twp, lds + r * FftCfg<N, EP>::LDSN, RowSlot{});
     if (live) {
 #pragma unroll
       for (int i = 0; i < E; ++i) out[base + t + T * i] = v[i];
