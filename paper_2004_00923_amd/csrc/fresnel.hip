@@ -330,6 +330,15 @@ __global__ __launch_bounds__(W *(N / fft_e(N, EP))) void fresnel_cols_persist(fl
   static_assert(FftCfg<N, EP>::P > 1, "persistent columns need an LDS exchange");
   typedef typename std::conditional<SPLIT, float, float2>::type Slot;
   __shared__ Slot lds[W * FftCfg<N, EP>::LDSN];
+  // twiddles from LDS (up to 2048 points), so that no global load issued after the
+  // next strip's prefetch makes the transform wait for it
+  constexpr bool kTwLds = N <= 2048;
+  __shared__ float2 tws[kTwLds ? N : 1];
+  if constexpr (kTwLds) {
+    for (int i = threadIdx.x; i < N; i += W * T) tws[i] = tw[i];
+    __syncthreads();
+  }
+  const float2 *twp = kTwLds ? tws : tw;
   const int c = threadIdx.x % W, t = threadIdx.x / W;
   const int strips = (nx + W - 1) / W, items = strips * nframes;
   auto where = [&](int item, size_t &off) {
@@ -339,23 +348,26 @@ __global__ __launch_bounds__(W *(N / fft_e(N, EP))) void fresnel_cols_persist(fl
     off = (size_t)f * N * nx + (live ? col : 0);
     return live;
   };
+  // Loads are unconditional (a dead column loads column 0 of its frame; past the
+  // last item the prefetch repeats the current strip), so no branch separates the
+  // prefetch from the transform.
   float2 cur[E], nxt[E];
   int item = blockIdx.x;
   size_t off = 0;
   bool live = item < items && where(item, off);
-  if (item < items) {
 #pragma unroll
-    for (int i = 0; i < E; ++i) cur[i] = live ? data[off + (size_t)(t + T * i) * nx] : make_float2(0.f, 0.f);
-  }
+  for (int i = 0; i < E; ++i) cur[i] = data[off + (size_t)(t + T * i) * nx];
   for (; item < items; item += gridDim.x) {
     const int item2 = item + gridDim.x;
-    size_t off2 = 0;
+    size_t off2 = off;
     const bool live2 = item2 < items && where(item2, off2);
-    if (item2 < items) {
 #pragma unroll
-      for (int i = 0; i < E; ++i) nxt[i] = live2 ? data[off2 + (size_t)(t + T * i) * nx] : make_float2(0.f, 0.f);
-    }
-    fft_passes<N, EP, 0, SPLIT>(cur, t, tw, lds, ColSlot<W>{c});
+    for (int i = 0; i < E; ++i) nxt[i] = data[off2 + (size_t)(t + T * i) * nx];
+    // the thread's position is made opaque per strip, so that the compiler
+    // recomputes the twiddle and LDS addresses instead of holding them in registers
+    int tk = t;
+    asm volatile("" : "+v"(tk));
+    fft_passes<N, EP, 0, SPLIT>(cur, tk, twp, lds, ColSlot<W>{c});
     if (live) {
       if constexpr (R16) {
 #pragma unroll
