@@ -338,16 +338,20 @@ void hh_graph_destroy(hh_graph *g);
  *              thread, 2 rows per group; 3 = 16 points per thread, one row per
  *              group; 4 and 5 = shapes 2 and 0 exchanging real and imaginary parts
  *              separately through half the LDS; 6 and 7 = shapes 3 and 2 as a
- *              persistent grid (eight one-wave groups per compute unit) that loads
- *              the next row while transforming the current one.  Shapes 1-7 exist for
- *              nx >= 512.
+ *              persistent grid (as many groups as the compute units hold) that
+ *              loads the next row while transforming the current one; 8 = the
+ *              persistent form with 16 points per thread, 4 rows per group and the
+ *              split exchange; 9 = the same with 2 rows per group and the full
+ *              exchange.  Shapes 1-9 exist for nx >= 512.
  *   fft_cols : column-FFT launch shape: 0 = 16 points per thread, 16 columns per
  *              group (fewer where the LDS does not hold them); 1 = 16 points, half
  *              as many columns; 2 = 32 points per thread; 3 and 4 = shapes 0 and 2
  *              with the split exchange; 5 and 6 = shapes 0 and 3 as a persistent grid
  *              (as many groups as the compute units hold) that loads the next strip
- *              while transforming the current one.
- *              Shapes 1-6 exist for ny >= 512.
+ *              while transforming the current one; 7 = shape 4 with the twiddles
+ *              staged in LDS and registers capped so that two groups share a
+ *              compute unit.
+ *              Shapes 1-7 exist for ny >= 512.
  *   gram_pxw : covariance split-K chunk, pixels per wavefront: 256, 512 or 1024
  *              (FP32 partial sums grow with it).
  *   gram_ref : reference m of the covariance's exact per-pixel split H = m 1^T + R

@@ -151,9 +151,12 @@ __global__ __launch_bounds__(ROWS *(N / fft_e(N, EP))) void fresnel_rows(
 
 // R16: instead of writing the column FFT back in place, write it scaled by
 // `scale` and rounded to FP16 (round to nearest even) into r16 [frames][N][nx].
-template <int N, int EP, int W, bool R16, bool SPLIT>
-__global__ __launch_bounds__(W *(N / fft_e(N, EP))) void fresnel_cols(float2 *__restrict__ data, int nx, const float2 *__restrict__ tw, h2 *__restrict__ r16,
-                  float scale) {
+// TWL: the twiddles are copied to LDS first (read there just before use, so that
+// the compiler does not hold all of them in registers from the start).
+template <int N, int EP, int W, bool R16, bool SPLIT, bool TWL = false>
+__global__ __launch_bounds__(W *(N / fft_e(N, EP)), TWL ? 4 : 1) void fresnel_cols(float2 *__restrict__ data, int nx,
+                                                               const float2 *__restrict__ tw, h2 *__restrict__ r16,
+                                                               float scale) {
   constexpr int E = FftCfg<N, EP>::E, T = FftCfg<N, EP>::T;
   const int c = threadIdx.x % W;
   const int t = threadIdx.x / W;
@@ -168,23 +171,35 @@ __global__ __launch_bounds__(W *(N / fft_e(N, EP))) void fresnel_cols(float2 *__
   if constexpr (FftCfg<N, EP>::P > 1) {
     typedef typename std::conditional<SPLIT, float, float2>::type Slot;
     __shared__ Slot lds[W * FftCfg<N, EP>::LDSN];
-    fft_passes<N, EP, 0, SPLIT>(v, t, tw, lds, ColSlot<W>{c});
+    __shared__ float2 tws[TWL ? N : 1];
+    if constexpr (TWL) {
+      for (int i = threadIdx.x; i < N; i += W * T) tws[i] = tw[i];
+      __syncthreads();
+    }
+    fft_passes<N, EP, 0, SPLIT>(v, t, TWL ? tws : tw, lds, ColSlot<W>{c});
   } else {
     fft_passes<N, EP, 0, false>(v, t, tw, (float2 *)nullptr, ColSlot<W>{c});
   }
-  if (live) {
+  // with TWL the thread index is made opaque here, so that the store addresses are
+  // formed after the transform instead of being kept in registers from the loads
+  int tid = threadIdx.x;
+  if constexpr (TWL) asm volatile("" : "+v"(tid));
+  const int ts = tid / W, cs = blockIdx.x * W + tid % W;
+  if (cs < nx) {
+    const size_t offs = (size_t)blockIdx.y * N * nx + cs;
+    float2 *bases = data + offs;
     if constexpr (R16) {
-      h2 *ob = r16 + off;
+      h2 *ob = r16 + offs;
 #pragma unroll
       for (int i = 0; i < E; ++i) {
         h2 q;
         q.x = (_Float16)(v[i].x * scale);
         q.y = (_Float16)(v[i].y * scale);
-        ob[(size_t)(t + T * i) * nx] = q;
+        ob[(size_t)(ts + T * i) * nx] = q;
       }
     } else {
 #pragma unroll
-      for (int i = 0; i < E; ++i) base[(size_t)(t + T * i) * nx] = v[i];
+      for (int i = 0; i < E; ++i) bases[(size_t)(ts + T * i) * nx] = v[i];
     }
   }
 }
@@ -238,18 +253,20 @@ __global__ __launch_bounds__(ROWS *(N / fft_e(N, EP))) void fresnel_rows_persist
   const int t = threadIdx.x % T, r = threadIdx.x / T;
   float *stage = reinterpret_cast<float *>(lds + r * FftCfg<N, EP>::LDSN);
   const int groups = (ny + ROWS - 1) / ROWS, items = groups * nframes;
-  float2 cx[E];
-#pragma unroll
-  for (int i = 0; i < E; ++i) cx[i] = chirp_x[t + T * i];
   // The twiddles come from LDS (up to 2048 points): a global twiddle load issued
   // after the next item's prefetch would make the transform wait for that prefetch.
+  // The row chirp, the same for every row, sits in LDS beside them.
   constexpr bool kTwLds = N <= 2048;
-  __shared__ float2 tws[kTwLds ? N : 1];
+  __shared__ float2 tws[kTwLds ? N : 1], cxs[kTwLds ? N : 1];
   if constexpr (kTwLds) {
-    for (int i = threadIdx.x; i < N; i += ROWS * T) tws[i] = tw[i];
+    for (int i = threadIdx.x; i < N; i += ROWS * T) {
+      tws[i] = tw[i];
+      cxs[i] = chirp_x[i];
+    }
     __syncthreads();
   }
   const float2 *twp = kTwLds ? tws : tw;
+  const float2 *cxp = kTwLds ? cxs : chirp_x;
   auto where = [&](int item, int &row, size_t &base, size_t &mbase) {
     const int f = item / groups;
     row = (item - f * groups) * ROWS + r;
@@ -271,7 +288,17 @@ __global__ __launch_bounds__(ROWS *(N / fft_e(N, EP))) void fresnel_rows_persist
     int row2 = 0;
     size_t base2 = 0, mbase2 = 0;
     const bool live2 = item2 < items && where(item2, row2, base2, mbase2);
-    const float2 cy = chirp_y[live ? row : 0];  // issued before the prefetch
+    // The thread index is made opaque for each item, so that nothing derived from it
+    // (the row chirp, LDS and twiddle addresses) is hoisted out of the loop and held
+    // in registers across it; the column chirp is loaded before the prefetch.
+    int tk = t;
+    asm volatile("" : "+v"(tk));
+    const float2 cy = chirp_y[live ? row : 0];
+    float2 cx[E];
+    if constexpr (!kTwLds) {
+#pragma unroll
+      for (int i = 0; i < E; ++i) cx[i] = chirp_x[tk + T * i];
+    }
     row_load<N, EP, IN>(nxt, src, mean, base2, mbase2, t, live2);
 #pragma unroll
     for (int l = 0; l < L; ++l) {
@@ -303,15 +330,15 @@ __global__ __launch_bounds__(ROWS *(N / fft_e(N, EP))) void fresnel_rows_persist
     float2 v[E];
 #pragma unroll
     for (int i = 0; i < E; ++i) {
-      const float val = stage[t + T * i];
-      const float2 c = cmul(cx[i], cy);
+      const float val = stage[tk + T * i];
+      const float2 c = cmul(kTwLds ? cxp[tk + T * i] : cx[i], cy);
       v[i] = make_float2(val * c.x, val * c.y);
     }
     __syncthreads();
-    fft_passes<N, EP, 0, SPLIT>(v, t, twp, lds + r * FftCfg<N, EP>::LDSN, RowSlot{});
+    fft_passes<N, EP, 0, SPLIT>(v, tk, twp, lds + r * FftCfg<N, EP>::LDSN, RowSlot{});
     if (live) {
 #pragma unroll
-      for (int i = 0; i < E; ++i) out[base + t + T * i] = v[i];
+      for (int i = 0; i < E; ++i) out[base + tk + T * i] = v[i];
     }
     __syncthreads();  // the LDS is reused by the next item
 #pragma unroll
@@ -433,7 +460,17 @@ template <int N, int EP, int R, bool SPLIT = false>
 hipError_t rows_persist_launch(const Plan &pl, int in_mode, const void *src, const float *mean, int nframes,
                                float2 *out, hipStream_t s) {
   const int items = (pl.ny + R - 1) / R * nframes;
-  const int grid = items < 8 * pl.cus ? items : 8 * pl.cus;  // one-wave groups: eight per compute unit
+  // as many groups as the compute units hold at once (LDS, registers)
+  static int per_cu = 0;
+  if (per_cu == 0) {
+    int occ = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, fresnel_rows_persist<N, EP, R, kInU16, SPLIT>,
+                                                     R * FftCfg<N, EP>::T, 0) != hipSuccess || occ < 1)
+      occ = 1;
+    per_cu = occ;
+  }
+  const int resident = per_cu * pl.cus;
+  const int grid = items < resident ? items : resident;
   dim3 g(grid), block(R * FftCfg<N, EP>::T);
   if (in_mode == kInU16)
     hipLaunchKernelGGL((fresnel_rows_persist<N, EP, R, kInU16, SPLIT>), g, block, 0, s, src, mean, pl.ny, nframes,
@@ -454,6 +491,8 @@ hipError_t rows_n(const Plan &pl, int shape, int in_mode, const void *src, const
   if constexpr (N >= kTunedMinN) {
     if (shape == 6) return rows_persist_launch<N, 16, 1>(pl, in_mode, src, mean, nframes, out, s);
     if (shape == 7) return rows_persist_launch<N, 32, 2>(pl, in_mode, src, mean, nframes, out, s);
+    if (shape == 8) return rows_persist_launch<N, 16, 4, true>(pl, in_mode, src, mean, nframes, out, s);
+    if (shape == 9) return rows_persist_launch<N, 16, 2>(pl, in_mode, src, mean, nframes, out, s);
     if (shape == 1) return rows_launch<N, 32, rows_per_wg<N, 32>()>(pl, in_mode, src, mean, nframes, out, s);
     if (shape == 2) return rows_launch<N, 32, 2>(pl, in_mode, src, mean, nframes, out, s);
     if (shape == 3) return rows_launch<N, 16, 1>(pl, in_mode, src, mean, nframes, out, s);
@@ -463,13 +502,15 @@ hipError_t rows_n(const Plan &pl, int shape, int in_mode, const void *src, const
   return rows_launch<N, 16, rows_per_wg<N, 16>()>(pl, in_mode, src, mean, nframes, out, s);
 }
 
-template <int N, int EP, int W, bool SPLIT = false>
+template <int N, int EP, int W, bool SPLIT = false, bool TWL = false>
 hipError_t cols_launch(const Plan &pl, int nframes, float2 *data, h2 *r16, float scale, hipStream_t s) {
   dim3 grid((pl.nx + W - 1) / W, nframes), block(W * FftCfg<N, EP>::T);
   if (r16)
-    hipLaunchKernelGGL((fresnel_cols<N, EP, W, true, SPLIT>), grid, block, 0, s, data, pl.nx, pl.tw_y, r16, scale);
+    hipLaunchKernelGGL((fresnel_cols<N, EP, W, true, SPLIT, TWL>), grid, block, 0, s, data, pl.nx, pl.tw_y, r16,
+                       scale);
   else
-    hipLaunchKernelGGL((fresnel_cols<N, EP, W, false, SPLIT>), grid, block, 0, s, data, pl.nx, pl.tw_y, r16, scale);
+    hipLaunchKernelGGL((fresnel_cols<N, EP, W, false, SPLIT, TWL>), grid, block, 0, s, data, pl.nx, pl.tw_y, r16,
+                       scale);
   return hipGetLastError();
 }
 
@@ -503,6 +544,8 @@ hipError_t cols_n(const Plan &pl, int shape, int nframes, float2 *data, h2 *r16,
   if constexpr (N >= kTunedMinN) {
     if (shape == 5) return cols_persist_launch<N, 16, cols_per_wg<N, 16>()>(pl, nframes, data, r16, scale, s);
     if (shape == 6) return cols_persist_launch<N, 16, cols_per_wg<N, 16>(), true>(pl, nframes, data, r16, scale, s);
+    if (shape == 7)
+      return cols_launch<N, 32, cols_per_wg<N, 32>(), true, (N <= 2048)>(pl, nframes, data, r16, scale, s);
     constexpr int Wh = cols_per_wg<N, 16>() / 2 > 0 ? cols_per_wg<N, 16>() / 2 : 1;
     if (shape == 1) return cols_launch<N, 16, Wh>(pl, nframes, data, r16, scale, s);
     if (shape == 2) return cols_launch<N, 32, cols_per_wg<N, 32>()>(pl, nframes, data, r16, scale, s);

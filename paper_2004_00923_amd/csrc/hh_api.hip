@@ -280,7 +280,7 @@ void put_tune(const hh_params &p, const Tune &t) {
 int default_group(const hh_params &p) { return fresnel_group_frames(p.nx, p.ny, 1 << 30, 0); }
 
 hh_status check_tune(const hh_params &p, const hh_tuning &t) {
-  const int nrows = p.nx >= 512 ? 8 : 1, ncols = p.ny >= 512 ? 7 : 1;
+  const int nrows = p.nx >= 512 ? 10 : 1, ncols = p.ny >= 512 ? 8 : 1;
   if (t.fft_rows < 0 || t.fft_rows >= nrows) return fail(HH_E_INVALID, "fft_rows=%d: %d shape(s) at nx=%d", t.fft_rows, nrows, p.nx);
   if (t.fft_cols < 0 || t.fft_cols >= ncols) return fail(HH_E_INVALID, "fft_cols=%d: %d shape(s) at ny=%d", t.fft_cols, ncols, p.ny);
   if (t.gram_pxw != 256 && t.gram_pxw != 512 && t.gram_pxw != 1024)
@@ -875,8 +875,8 @@ hh_status hh_autotune(const hh_params *p, const uint16_t *frames, void *workspac
   // coordinate descent: row shape, column shape, group size, split-K chunk
   const int dg = default_group(*p);
   std::vector<std::pair<int Tune::*, std::vector<int>>> axes = {
-      {&Tune::rows, p->nx >= 512 ? std::vector<int>{0, 1, 2, 3, 4, 5, 6, 7} : std::vector<int>{0}},
-      {&Tune::cols, p->ny >= 512 ? std::vector<int>{0, 1, 2, 3, 4, 5, 6} : std::vector<int>{0}},
+      {&Tune::rows, p->nx >= 512 ? std::vector<int>{0, 1, 2, 3, 4, 5, 6, 7, 8, 9} : std::vector<int>{0}},
+      {&Tune::cols, p->ny >= 512 ? std::vector<int>{0, 1, 2, 3, 4, 5, 6, 7} : std::vector<int>{0}},
       {&Tune::group, {0, std::max(1, dg / 2), std::max(1, dg / 4), std::min(2 * dg, p->nt), std::min(4 * dg, p->nt)}},
       {&Tune::pxw, {256, 512, 1024}},
       {&Tune::gram_ref, {0, 1}}};

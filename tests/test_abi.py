@@ -203,7 +203,7 @@ def test_tuning_validation_and_roundtrip():
     # FFT choices follow (nx, ny); the split-K chunk follows (nx * ny, nt, precision)
     q = hh.Params(nx=1024, ny=1024, nt=16, k_lo=2, k_hi=15)
     assert hh.tuning_get(q)["fft_rows"] == 1 and hh.tuning_get(q)["gram_pxw"] == 256
-    for bad in ({"fft_rows": 8}, {"fft_cols": 7}, {"gram_pxw": 300}, {"group": -1}, {"group": 33}, {"gram_ref": 2}):
+    for bad in ({"fft_rows": 10}, {"fft_cols": 8}, {"gram_pxw": 300}, {"group": -1}, {"group": 33}, {"gram_ref": 2}):
         with pytest.raises(hh.HHError) as ei:
             hh.tuning_set(p, **bad)
         assert ei.value.status == hh.HH_E_INVALID

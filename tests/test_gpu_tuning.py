@@ -43,8 +43,9 @@ def case(hh):
 
 @pytest.mark.parametrize("rows,cols,pxw,group", [(0, 0, 256, 0), (1, 0, 256, 0), (2, 0, 256, 0), (3, 0, 256, 0),
                                                  (4, 0, 256, 0), (5, 0, 256, 0), (6, 0, 256, 0), (7, 0, 256, 0),
+                                                 (8, 0, 256, 0), (9, 0, 256, 0),
                                                  (0, 1, 256, 0), (0, 2, 256, 0), (0, 3, 256, 0), (0, 4, 256, 0),
-                                                 (0, 5, 256, 0), (0, 6, 256, 0), (0, 0, 512, 0), (0, 0, 1024, 0),
+                                                 (0, 5, 256, 0), (0, 6, 256, 0), (0, 7, 256, 0), (0, 0, 512, 0), (0, 0, 1024, 0),
                                                  (0, 0, 256, 3), (2, 2, 1024, 1), (6, 5, 512, 32), (7, 6, 256, 5)])
 @pytest.mark.parametrize("precision,gram_ref", [("fp32", 0), ("fp32", 1), ("fp16store", 0)])
 def test_every_launch_choice_meets_the_bar(hh, case, rows, cols, pxw, group, precision, gram_ref):
