@@ -336,53 +336,54 @@ __global__ __launch_bounds__(threads_for<NMAX>()) void eigh_jacobi(EighBatch bat
         int p1, q1, p2, q2;
         pair_of(r, bP[u], m, p1, q1);
         pair_of(r, bQ[u], m, p2, q2);
-        if (bP[u] == bQ[u]) {
-          if (q1 < n) {
-            // the pair's own 2x2 block: zeroed off-diagonal and moved diagonal if rotated
-            const bool rot = P.rot[p1] != 0;
-            const double dp = rot ? P.d[p1] : A[p1 * LD + p1].x;
-            const double dq = rot ? P.d[q1] : A[q1 * LD + q1].x;
-            const double2 x = rot ? make_double2(0.0, 0.0) : A[p1 * LD + q1];
-            A[p1 * LD + p1] = make_double2(dp, 0.0);
-            A[q1 * LD + q1] = make_double2(dq, 0.0);
-            A[p1 * LD + q1] = x;
-            A[q1 * LD + p1] = zconj(x);
-          }
-        } else {
-          const bool vq1 = q1 < n, vq2 = q2 < n;
-          // value selects (clamped indices), never a select between LDS and a local
-          const int q1c = vq1 ? q1 : p1, q2c = vq2 ? q2 : p2;
-          const double m1 = vq1 ? 1.0 : 0.0, m2 = vq2 ? 1.0 : 0.0;
-          const double2 a = A[p1 * LD + p2];
-          const double2 b = zscale(A[p1 * LD + q2c], m2);
-          const double2 d = zscale(A[q1c * LD + p2], m1);
-          const double2 f = zscale(A[q1c * LD + q2c], m1 * m2);
-          // T = M J2 (columns p2, q2), then J1^H T (rows p1, q1)
-          const double c1 = P.c[p1], c2 = P.c[p2];
-          const double2 e1 = zscale(P.e[q1c], m1);  // J[p1][q1]
-          const double2 e2 = zscale(P.e[q2c], m2);  // J[p2][q2]
-          const double2 me2c = make_double2(-e2.x, e2.y);  // J[q2][p2]
-          const double2 t00 = zadd(zscale(a, c2), zmul(b, me2c)), t01 = zadd(zmul(a, e2), zscale(b, c2));
-          const double2 t10 = zadd(zscale(d, c2), zmul(f, me2c)), t11 = zadd(zmul(d, e2), zscale(f, c2));
-          const double2 o00 = zsub(zscale(t00, c1), zmul(e1, t10));
-          const double2 o01 = zsub(zscale(t01, c1), zmul(e1, t11));
-          const double2 e1c = zconj(e1);
-          const double2 o10 = zadd(zmul(e1c, t00), zscale(t10, c1));
-          const double2 o11 = zadd(zmul(e1c, t01), zscale(t11, c1));
-          A[p1 * LD + p2] = o00;
-          A[p2 * LD + p1] = zconj(o00);
-          if (vq2) {
-            A[p1 * LD + q2] = o01;
-            A[q2 * LD + p1] = zconj(o01);
-          }
-          if (vq1) {
-            A[q1 * LD + p2] = o10;
-            A[p2 * LD + q1] = zconj(o10);
-          }
-          if (vq1 && vq2) {
-            A[q1 * LD + q2] = o11;
-            A[q2 * LD + q1] = zconj(o11);
-          }
+        // One instruction stream for the pair's own block (P == Q) and the others:
+        // every operand is loaded first; on the own block the rotated values are
+        // replaced by the exact ones (zero off-diagonal, moved diagonal) or, when the
+        // pair does not rotate, by the entries as they were.
+        const bool own = bP[u] == bQ[u];
+        const bool vq1 = q1 < n, vq2 = q2 < n;
+        // value selects (clamped indices), never a select between LDS and a local
+        const int q1c = vq1 ? q1 : p1, q2c = vq2 ? q2 : p2;
+        const double m1 = vq1 ? 1.0 : 0.0, m2 = vq2 ? 1.0 : 0.0;
+        const double2 a = A[p1 * LD + p2];
+        const double2 b = zscale(A[p1 * LD + q2c], m2);
+        const double2 d = zscale(A[q1c * LD + p2], m1);
+        const double2 f = zscale(A[q1c * LD + q2c], m1 * m2);
+        const double c1 = P.c[p1], c2 = P.c[p2];
+        const double2 e1 = zscale(P.e[q1c], m1);  // J[p1][q1]
+        const double2 e2 = zscale(P.e[q2c], m2);  // J[p2][q2]
+        const bool rot = P.rot[p1] != 0;
+        const double dp = P.d[p1], dq = P.d[q1c];
+        // T = M J2 (columns p2, q2), then J1^H T (rows p1, q1)
+        const double2 me2c = make_double2(-e2.x, e2.y);  // J[q2][p2]
+        const double2 t00 = zadd(zscale(a, c2), zmul(b, me2c)), t01 = zadd(zmul(a, e2), zscale(b, c2));
+        const double2 t10 = zadd(zscale(d, c2), zmul(f, me2c)), t11 = zadd(zmul(d, e2), zscale(f, c2));
+        double2 o00 = zsub(zscale(t00, c1), zmul(e1, t10));
+        double2 o01 = zsub(zscale(t01, c1), zmul(e1, t11));
+        const double2 e1c = zconj(e1);
+        double2 o10 = zadd(zmul(e1c, t00), zscale(t10, c1));
+        double2 o11 = zadd(zmul(e1c, t01), zscale(t11, c1));
+        if (own) {
+          o00 = make_double2(rot ? dp : a.x, 0.0);
+          o11 = make_double2(rot ? dq : f.x, 0.0);
+          o01 = rot ? make_double2(0.0, 0.0) : b;
+          o10 = zconj(o01);
+        }
+        // on the own block the mirrored write of a diagonal entry is to the same
+        // address: it goes first, so that the entry keeps a +0 imaginary part
+        A[p2 * LD + p1] = zconj(o00);
+        A[p1 * LD + p2] = o00;
+        if (vq2) {
+          A[q2 * LD + p1] = zconj(o01);
+          A[p1 * LD + q2] = o01;
+        }
+        if (vq1) {
+          A[p2 * LD + q1] = zconj(o10);
+          A[q1 * LD + p2] = o10;
+        }
+        if (vq1 && vq2) {
+          A[q2 * LD + q1] = zconj(o11);
+          A[q1 * LD + q2] = o11;
         }
       }
       __syncthreads();
@@ -395,20 +396,36 @@ __global__ __launch_bounds__(threads_for<NMAX>()) void eigh_jacobi(EighBatch bat
           set_rotation(prm[pb ^ 1], tid, p, q, n, A[p * LD + p].x, A[qc * LD + qc].x, A[p * LD + qc], abs2);
         }
       } else {
-        // (2b) waves 1..3: V <- V J, one (row, pair) item at a time, in place
+        // (2b) waves 1..3: V <- V J on (row, pair) items in place: every operand is
+        // loaded first, then the items are rotated (a pair that does not rotate has
+        // c = 1, e = 0 and is rotated all the same: no dependent branch)
+        constexpr int VC = NMAX <= 32 ? VPT : 2;  // items loaded together (registers)
 #pragma unroll
-        for (int u = 0; u < VPT; ++u) {
-          if (vRow[u] >= 0) {
-            const int row = vRow[u];
-            int p, q;
-            pair_of(r, vK[u], m, p, q);
-            if (q < n && P.rot[p]) {
-              const double2 vp = V[row * LD + p], vq = V[row * LD + q];
-              const double c = P.c[p];
-              const double2 eq = P.e[q];  // J[p][q]
-              const double2 ep = P.e[p];  // J[q][p]
-              V[row * LD + p] = zadd(zscale(vp, c), zmul(vq, ep));
-              V[row * LD + q] = zadd(zmul(vp, eq), zscale(vq, c));
+        for (int u0 = 0; u0 < VPT; u0 += VC) {
+          double2 vp[VC], vq[VC], eq[VC], ep[VC];
+          double cc[VC];
+          int ip[VC], iq[VC];
+#pragma unroll
+          for (int w = 0; w < VC; ++w) {
+            const int u = u0 + w < VPT ? u0 + w : VPT - 1;
+            const bool ok = u0 + w < VPT && vRow[u] >= 0;
+            int p = 0, q = 0;
+            if (ok) pair_of(r, vK[u], m, p, q);
+            const int row = ok ? vRow[u] : 0;
+            const int qc = q < n ? q : p;
+            ip[w] = row * LD + p;
+            iq[w] = ok && q < n ? row * LD + q : -1;
+            vp[w] = V[row * LD + p];
+            vq[w] = V[row * LD + qc];
+            cc[w] = P.c[p];
+            eq[w] = P.e[qc];  // J[p][q]
+            ep[w] = P.e[p];   // J[q][p]
+          }
+#pragma unroll
+          for (int w = 0; w < VC; ++w) {
+            if (iq[w] >= 0) {
+              V[ip[w]] = zadd(zscale(vp[w], cc[w]), zmul(vq[w], ep[w]));
+              V[iq[w]] = zadd(zmul(vp[w], eq[w]), zscale(vq[w], cc[w]));
             }
           }
         }
