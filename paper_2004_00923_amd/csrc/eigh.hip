@@ -91,31 +91,26 @@ __device__ __forceinline__ void set_rotation(RoundParams<NMAX> &P, int k, int p,
     P.e[p] = make_double2(0.0, 0.0);
     return;
   }
+  // computed whether or not the pair rotates, then selected (no branch around the
+  // arithmetic; a pair that does not rotate gets c = 1, e = 0 and its diagonal as is)
   const double ab2 = beta.x * beta.x + beta.y * beta.y;
-  if (ab2 > kRelTol * kRelTol * fabs(a * b) && ab2 > abs2) {
-    const double g = b - a, ag = fabs(g), sg = g >= 0.0 ? 1.0 : -1.0;
-    const double w = g * g + 4.0 * ab2;
-    const double D = w * rsq64(w);
-    const double inv = rsq64(2.0 * D * (D + ag));  // 1 / den
-    const double tab = sg * 2.0 * ab2 * rcp64(D + ag);
-    const double c = (D + ag) * inv;
-    const double2 eq = make_double2(sg * 2.0 * inv * beta.x, sg * 2.0 * inv * beta.y);  // J[p][q]
-    P.c[p] = c;
-    P.c[q] = c;
-    P.e[q] = eq;
-    P.e[p] = make_double2(-eq.x, eq.y);  // J[q][p] = -conj(J[p][q])
-    P.d[p] = a - tab;
-    P.d[q] = b + tab;
-    P.rot[p] = 1;
-    P.rot[q] = 1;
-  } else {
-    P.c[p] = 1.0;
-    P.c[q] = 1.0;
-    P.e[p] = make_double2(0.0, 0.0);
-    P.e[q] = make_double2(0.0, 0.0);
-    P.rot[p] = 0;
-    P.rot[q] = 0;
-  }
+  const bool rot = ab2 > kRelTol * kRelTol * fabs(a * b) && ab2 > abs2;
+  const double g = b - a, ag = fabs(g), sg = g >= 0.0 ? 1.0 : -1.0;
+  const double w = g * g + 4.0 * ab2;
+  const double D = w * rsq64(w);
+  const double inv = rsq64(2.0 * D * (D + ag));  // 1 / den
+  const double tab = sg * 2.0 * ab2 * rcp64(D + ag);
+  const double c = rot ? (D + ag) * inv : 1.0;
+  const double2 eq = rot ? make_double2(sg * 2.0 * inv * beta.x, sg * 2.0 * inv * beta.y)  // J[p][q]
+                         : make_double2(0.0, 0.0);
+  P.c[p] = c;
+  P.c[q] = c;
+  P.e[q] = eq;
+  P.e[p] = rot ? make_double2(-eq.x, eq.y) : make_double2(0.0, 0.0);  // J[q][p] = -conj(J[p][q])
+  P.d[p] = rot ? a - tab : a;
+  P.d[q] = rot ? b + tab : b;
+  P.rot[p] = rot ? 1 : 0;
+  P.rot[q] = rot ? 1 : 0;
 }
 
 // C into A (scaled by an exact power of two so that its Frobenius norm is O(1))
