@@ -89,3 +89,20 @@ def test_frame0_reference_covariance(hh, nt, ny, nx):
         hh.tuning_reset()
     say(f"frame-0 reference covariance {nt}x{ny}x{nx}: {e:.2e}")
     assert e <= 2e-6
+
+
+@pytest.mark.parametrize("ny,nx", [(2048, 512), (512, 2048), (4096, 512), (512, 4096)])
+@pytest.mark.parametrize("rows,cols", [(8, 7), (9, 7), (6, 5)])
+def test_persistent_and_capped_shapes_at_other_lengths(hh, ny, nx, rows, cols):
+    # the four-row and two-row persistent row FFTs and the register-capped column FFT
+    # (LDS twiddles up to 2048 points, global twiddles beyond) at 512-4096 points
+    f = gen_stack(ny + nx + rows, 8, ny, nx)
+    r = oracle.pipeline_ref(f, LAM, Z, PITCH, 1, 7)
+    p = hh.Params(nx=nx, ny=ny, nt=8, k_lo=1, k_hi=7)
+    hh.tuning_set(p, fft_rows=rows, fft_cols=cols)
+    try:
+        e = rel(_run(hh, p, to_dev(f)), r["image"])
+    finally:
+        hh.tuning_reset()
+    say(f"shapes rows={rows} cols={cols} 8x{ny}x{nx}: image {e:.2e}")
+    assert e <= IMG_TOL
