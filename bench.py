@@ -81,9 +81,12 @@ def algorithmic_bytes(kernel: str, launches_per_step: int) -> float:
 
 
 # Launch choices for the 1024^2 x 32 workload, picked by the autotuner (hh_autotune)
-# and pinned so that runs are reproducible and comparable with the counter runs
-# below; --autotune reruns the tuner instead.
-PINNED_TUNING = {"fp32": "8,7,512,32,1", "fp16store": "8,7,256,16,0", "exact": "8,7,1024,16,0"}
+# or by timing the candidate shapes with --tuning, and pinned so that runs are
+# reproducible and comparable with the counter runs below; --autotune reruns the
+# tuner instead.
+PINNED_TUNING = {"fp32": "8,7,512,32,1", "fp16store": "8,7,256,16,0", "exact": "8,7,1024,16,0",
+                 "bf16": "8,7,256,32,0", "bf16x3": "8,7,256,32,0", "fp16": "8,7,256,32,0", "fp16x3": "8,7,256,32,0",
+                 "fp8e4m3": "8,7,256,32,0"}
 
 # HBM bytes per launch measured with rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE (fetch
 # counter scaled by 2.000 and write by 1.000, the factors a plain 256 MiB copy gives),

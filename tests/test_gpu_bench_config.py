@@ -40,8 +40,7 @@ def p_key(form):
 
 
 def _params(hh, form):
-    precision, proj = {"fp32": ("fp32", "auto"), "fp16store": ("fp16store", "auto"), "exact": ("exact", "auto"),
-                       "first": ("exact", "first")}[form]
+    precision, proj = {"first": ("exact", "first")}.get(form, (form, "auto"))
     p = hh.Params(nx=NX, ny=NY, nt=NT, k_lo=K_LO, k_hi=K_HI, precision=hh.PRECISIONS[precision],
                   proj_mode=hh.PROJ_MODES[proj])
     vals = [int(v) for v in bench.PINNED_TUNING[precision].split(",")]
@@ -49,8 +48,11 @@ def _params(hh, form):
     return p
 
 
-@pytest.mark.parametrize("form,tol", [("fp32", 1e-5), ("exact", 1e-5), ("first", 1e-5), ("fp16store", 1e-3)])
-def test_bench_forms_at_full_size(hh, stack, form, tol):
+@pytest.mark.parametrize("form,tol,lam_tol", [("fp32", 1e-5, 1e-6), ("exact", 1e-5, 1e-6), ("first", 1e-5, 1e-6),
+                                              ("fp16store", 1e-3, 1e-6), ("bf16x3", 1e-5, 1e-6),
+                                              ("fp16x3", 1e-5, 1e-6), ("bf16", 1e-3, 1e-6), ("fp16", 1e-3, 1e-6),
+                                              ("fp8e4m3", 1e-3, 1e-5)])
+def test_bench_forms_at_full_size(hh, stack, form, tol, lam_tol):
     import torch
     f, ref = stack
     p = _params(hh, form)
@@ -65,7 +67,7 @@ def test_bench_forms_at_full_size(hh, stack, form, tol):
         hh.tuning_reset()
     say(f"bench configuration {form} ({bench.PINNED_TUNING[p_key(form)]}): image {e:.2e} lambda {e_lam:.2e}")
     assert e <= tol
-    assert e_lam <= 1e-6
+    assert e_lam <= lam_tol
 
 
 def test_bench_batches_on_streams_equal_single_stacks(hh):
