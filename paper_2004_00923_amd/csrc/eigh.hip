@@ -26,11 +26,11 @@ namespace {
 
 constexpr double kRelTol = 1e-15;
 constexpr double kAbsTol = 1e-18;
-// threads per problem: 320 for n <= 32 (rounds are latency-bound; wave 0 computes
-// the rotations while four waves rotate V, two (row, pair) items each), 1024 for
+// threads per problem: 576 for n <= 32 (rounds are latency-bound; wave 0 computes
+// the rotations while eight waves rotate V, one (row, pair) item each), 1024 for
 // n <= 64 (a round has four times the 2x2 blocks and V items, so it is throughput-bound)
 template <int NMAX>
-constexpr int threads_for() { return NMAX <= 32 ? 320 : 1024; }
+constexpr int threads_for() { return NMAX <= 32 ? 576 : 1024; }
 constexpr size_t kCuLdsBytes = 160 * 1024;
 
 __device__ __forceinline__ double2 zmul(double2 a, double2 b) {
