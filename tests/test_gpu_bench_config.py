@@ -10,7 +10,7 @@ import pytest
 
 import bench
 import oracle
-from gpu_util import LAM, PITCH, Z, rel, say, to_dev, to_np
+from gpu_util import LAM, PITCH, Z, eig_parity, fmt_eig, rel, say, to_dev, to_np
 from paper_2004_00923_amd.synth import gen_stack
 
 pytestmark = pytest.mark.gpu
@@ -48,11 +48,13 @@ def _params(hh, form):
     return p
 
 
-@pytest.mark.parametrize("form,tol,lam_tol", [("fp32", 1e-5, 1e-6), ("exact", 1e-5, 1e-6), ("first", 1e-5, 1e-6),
-                                              ("fp16store", 1e-3, 1e-6), ("bf16x3", 1e-5, 1e-6),
-                                              ("fp16x3", 1e-5, 1e-6), ("bf16", 1e-3, 1e-6), ("fp16", 1e-3, 1e-6),
-                                              ("fp8e4m3", 1e-3, 1e-5)])
-def test_bench_forms_at_full_size(hh, stack, form, tol, lam_tol):
+# form, image bound, eigenvalue bound (/ lambda_0), covariance bound (normwise)
+@pytest.mark.parametrize("form,tol,lam_tol,c_tol", [("fp32", 1e-5, 1e-6, 2e-6), ("exact", 1e-5, 1e-6, 1e-12),
+                                                    ("first", 1e-5, 1e-6, 1e-12), ("fp16store", 1e-3, 1e-6, 1e-5),
+                                                    ("bf16x3", 1e-5, 1e-6, 2e-6), ("fp16x3", 1e-5, 1e-6, 2e-6),
+                                                    ("bf16", 1e-3, 1e-6, 1e-5), ("fp16", 1e-3, 1e-6, 1e-5),
+                                                    ("fp8e4m3", 1e-3, 1e-5, 1e-4)])
+def test_bench_forms_at_full_size(hh, stack, form, tol, lam_tol, c_tol):
     import torch
     f, ref = stack
     p = _params(hh, form)
@@ -60,12 +62,16 @@ def test_bench_forms_at_full_size(hh, stack, form, tol, lam_tol):
         ws = hh.alloc_workspace(hh.workspace_bytes(p))
         img = torch.empty((NY, NX), dtype=torch.float32, device="cuda")
         ev = torch.empty(NT, dtype=torch.float64, device="cuda")
-        hh.hh_pipeline(p, to_dev(f), img, ws, ev)
+        V = torch.empty((NT, NT), dtype=torch.complex128, device="cuda")
+        hh.hh_pipeline(p, to_dev(f), img, ws, ev, V)
         e = rel(to_np(img), ref["image"])
-        e_lam = float(np.abs(to_np(ev) - ref["evals"]).max() / ref["evals"][0])
+        w = to_np(ev)
+        e_lam = float(np.abs(w - ref["evals"]).max() / ref["evals"][0])
+        d = eig_parity(w, to_np(V), ref, K_LO, K_HI, c_tol, f"bench form {form}")
     finally:
         hh.tuning_reset()
-    say(f"bench configuration {form} ({bench.PINNED_TUNING[p_key(form)]}): image {e:.2e} lambda {e_lam:.2e}")
+    say(f"bench configuration {form} ({bench.PINNED_TUNING[p_key(form)]}): image {e:.2e} lambda {e_lam:.2e} "
+        f"{fmt_eig(d)}")
     assert e <= tol
     assert e_lam <= lam_tol
 

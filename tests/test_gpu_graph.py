@@ -7,7 +7,7 @@ import numpy as np
 import pytest
 
 import oracle
-from gpu_util import LAM, PITCH, Z, rel, say, to_dev, to_np
+from gpu_util import LAM, PITCH, Z, eig_parity, fmt_eig, rel, say, to_dev, to_np
 from paper_2004_00923_amd.synth import gen_stack
 
 pytestmark = pytest.mark.gpu
@@ -86,8 +86,11 @@ def test_graph_replays_equal_eager(hh, form):
 
 def test_graph_batch_matches_oracle(hh):
     # the first three stacks cover every frame shape and every stack length
+    import torch
     ps, frames, imgs, host, ws = _setup(hh)
-    g = hh.Graph(ps, frames, imgs, ws)
+    evs = [torch.empty(p.nt, dtype=torch.float64, device="cuda") for p in ps]
+    vecs = [torch.empty((p.nt, p.nt), dtype=torch.complex128, device="cuda") for p in ps]
+    g = hh.Graph(ps, frames, imgs, ws, evals=evs, evecs=vecs)
     g.launch()
     out = [to_np(m) for m in imgs]
     g.close()
@@ -96,7 +99,8 @@ def test_graph_batch_matches_oracle(hh):
         say(f"oracle for stack {i}: {p.nt}x{p.ny}x{p.nx}")
         r = oracle.pipeline_ref(host[i], LAM, Z, PITCH, p.k_lo, p.k_hi)
         e = rel(out[i], r["image"])
-        say(f"stack {i}: image error {e:.2e}")
+        d = eig_parity(to_np(evs[i]), to_np(vecs[i]), r, p.k_lo, p.k_hi, 2e-6, f"graph stack {i}")
+        say(f"stack {i}: image error {e:.2e} {fmt_eig(d)}")
         assert e <= IMG_TOL
 
 

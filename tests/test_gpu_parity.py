@@ -5,7 +5,7 @@ import numpy as np
 import pytest
 
 import oracle
-from gpu_util import LAM, PITCH, Z, rel, say, to_dev, to_np
+from gpu_util import LAM, PITCH, Z, eig_parity, fmt_eig, rel, say, to_dev, to_np
 from paper_2004_00923_amd.synth import gen_stack
 
 pytestmark = pytest.mark.gpu
@@ -231,11 +231,9 @@ def _pipeline_check(hh, frames, k_lo, k_hi):
     r = oracle.pipeline_ref(frames, LAM, Z, PITCH, k_lo, k_hi)
     e_img = rel(M, r["image"])
     e_lam = np.abs(w - r["evals"]).max() / r["evals"][0]
-    Pk = V[:, k_lo:k_hi + 1] @ V[:, k_lo:k_hi + 1].conj().T
-    Pr = r["evecs"][:, k_lo:k_hi + 1] @ r["evecs"][:, k_lo:k_hi + 1].conj().T
-    e_proj = np.linalg.norm(Pk - Pr, 2)
+    d = eig_parity(w, V, r, k_lo, k_hi, C_TOL, f"pipeline {frames.shape}")
     say(f"pipeline {frames.shape} PCs {k_lo}..{k_hi}: image {e_img:.2e} lambda {e_lam:.2e} "
-        f"projector {e_proj:.2e} sweeps {info}")
+        f"(each {d['lam_rel_each']:.1e}) {fmt_eig(d)} sweeps {info}")
     assert info >= 0
     assert e_img <= IMG_TOL
     assert e_lam <= 1e-6
@@ -273,7 +271,7 @@ def test_pipeline_batch_uneven_matches_alone_and_oracle(hh):
     # reduction) and the oracle within the FP32 bar
     import torch
     specs = [(16, 64, 64, 2), (32, 32, 128, 2), (64, 64, 32, 3), (32, 128, 128, 2), (8, 16, 16, 1)]
-    ps, frames, imgs, evs = [], [], [], []
+    ps, frames, imgs, evs, vecs = [], [], [], [], []
     host = []
     for i, (nt, ny, nx, k_lo) in enumerate(specs):
         f = gen_stack(100 + i, nt, ny, nx)
@@ -282,8 +280,9 @@ def test_pipeline_batch_uneven_matches_alone_and_oracle(hh):
         frames.append(to_dev(f))
         imgs.append(torch.empty((ny, nx), dtype=torch.float32, device="cuda"))
         evs.append(torch.empty(nt, dtype=torch.float64, device="cuda"))
+        vecs.append(torch.empty((nt, nt), dtype=torch.complex128, device="cuda"))
     ws = hh.alloc_workspace(hh.batch_workspace_bytes(ps))
-    hh.hh_pipeline_batch(ps, frames, imgs, ws, evals=evs)
+    hh.hh_pipeline_batch(ps, frames, imgs, ws, evals=evs, evecs=vecs)
     for i, (nt, ny, nx, k_lo) in enumerate(specs):
         say(f"batch stack {i}: {nt}x{ny}x{nx}")
         M = to_np(imgs[i])
@@ -292,6 +291,8 @@ def test_pipeline_batch_uneven_matches_alone_and_oracle(hh):
         r = oracle.pipeline_ref(host[i], LAM, Z, PITCH, k_lo, nt - 1)
         assert rel(M, r["image"]) <= IMG_TOL
         assert np.abs(to_np(evs[i]) - r["evals"]).max() <= 1e-6 * r["evals"][0]
+        d = eig_parity(to_np(evs[i]), to_np(vecs[i]), r, k_lo, nt - 1, C_TOL, f"batch stack {i}")
+        say(f"  {fmt_eig(d)}")
 
 
 def test_pipeline_batch_repeated_launch(hh):
