@@ -173,6 +173,21 @@ hh_status hh_covariance(const hh_params *p, const float *holo, double *cov,
                         void *workspace, size_t ws_bytes, void *stream);
 
 /*
+ * hh_covariance without a workspace argument, for callers that cannot allocate
+ * device memory (code under HIP graph capture, serving loops and harnesses that
+ * forbid hipMalloc).  Same arguments, launch, results and errors as
+ * hh_covariance; the split-K partials live in a static device array of
+ * hh_covariance_noalloc_max_bytes() bytes (48 MiB), one per GPU, held until the
+ * process ends.  No call allocates or frees device memory.  Sizes whose partials
+ * do not fit (above about 2M pixels at nt <= 32, 0.5M at nt > 32, with the default
+ * 256-pixel chunk) return HH_E_UNSUPPORTED and enqueue nothing.  Every call on a
+ * GPU shares that GPU's array: calls that overlap on one GPU (other streams,
+ * other threads) race and must be ordered by the caller.
+ */
+hh_status hh_covariance_noalloc(const hh_params *p, const float *holo, double *cov, void *stream);
+size_t hh_covariance_noalloc_max_bytes(void);
+
+/*
  * Step (b) without step (a): C of Eq. (4) computed exactly from the frames as
  * nx ny I^T I (I[p][t] the uint16 interferograms; exact because Eq. (1) as
  * discretised is a unit-modulus chirp followed by an unnormalised DFT).  Every

@@ -549,6 +549,61 @@ hh_status hh_covariance(const hh_params *p, const float *holo, double *cov, void
   return HH_OK;
 }
 
+// ------------------------------------------------------- allocation-free ----
+// Device scratch of hh_covariance_noalloc: the covariance's split-K partials.  One
+// copy per GPU, held until the process ends.  Host code never uses the array's name
+// as an address: each device's copy is looked up once with hipGetSymbolAddress and
+// that pointer is what the kernels receive.
+constexpr size_t kNoAllocScratchBytes = size_t(48) << 20;
+static __device__ __align__(256) char scratch[kNoAllocScratchBytes];
+
+namespace {
+std::mutex g_scratch_mu;
+std::map<int, char *> g_scratch_ptr;  // device -> address of that device's scratch
+
+// The current device's scratch address (looked up on its first use on that device).
+hh_status scratch_ptr(char **out) {
+  const int dev = current_device();
+  if (dev < 0) return fail(HH_E_DEVICE, "hh_covariance_noalloc: no current HIP device");
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  auto it = g_scratch_ptr.find(dev);
+  if (it == g_scratch_ptr.end()) {
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) return device_fail(e != hipSuccess ? e : hipErrorInvalidSymbol, "hipGetSymbolAddress");
+    it = g_scratch_ptr.emplace(dev, static_cast<char *>(ptr)).first;
+  }
+  *out = it->second;
+  return HH_OK;
+}
+}  // namespace
+
+size_t hh_covariance_noalloc_max_bytes(void) { return kNoAllocScratchBytes; }
+
+hh_status hh_covariance_noalloc(const hh_params *p, const float *holo, double *cov, void *stream) {
+  hh_status st;
+  if ((st = check_stack(p)) || (st = check_precision(p, false))) return st;
+  if (!holo || !cov) return fail(HH_E_INVALID, "holo and cov must be non-NULL");
+  if (!aligned(holo, 16) || !aligned(cov, 16)) return fail(HH_E_INVALID, "holo/cov misaligned");
+  const long long npix = (long long)p->nx * p->ny;
+  // the same launch as hh_covariance: the same split-K chunk and reference
+  GramLayout gl = gram_layout(p->nt, npix, get_tune(*p).pxw);
+  gl.ref = get_tune(*p).gram_ref;
+  const size_t need = align_up(gl.partial_bytes) + align_up(gl.partial2_bytes);
+  if (need > kNoAllocScratchBytes)
+    return fail(HH_E_UNSUPPORTED,
+                "hh_covariance_noalloc: nt=%d, %lld pixels at %d-pixel chunks need %zu bytes of scratch; the "
+                "static scratch holds %zu (use hh_covariance with a workspace)",
+                p->nt, npix, gl.pxw, need, kNoAllocScratchBytes);
+  char *ws = nullptr;
+  if ((st = scratch_ptr(&ws))) return st;
+  hipError_t e = launch_gram(gl, reinterpret_cast<const float2 *>(holo), p->nt, npix, reinterpret_cast<double *>(ws),
+                             reinterpret_cast<double *>(ws + align_up(gl.partial_bytes)), cov, (hipStream_t)stream,
+                             p->precision);
+  if (e != hipSuccess) return device_fail(e, "hh_covariance_noalloc");
+  return HH_OK;
+}
+
 hh_status hh_covariance_frames(const hh_params *p, const uint16_t *frames, double *cov, void *workspace,
                                size_t ws_bytes, void *stream) {
   hh_status st;

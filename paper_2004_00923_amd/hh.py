@@ -95,6 +95,8 @@ SIGNATURES = {
     "hh_fresnel": (ctypes.c_int32, [ctypes.POINTER(hh_params), _P, ctypes.c_int32, _P, _P]),
     "hh_covariance": (ctypes.c_int32, [ctypes.POINTER(hh_params), _P, _P, _P, ctypes.c_size_t, _P]),
     "hh_covariance_frames": (ctypes.c_int32, [ctypes.POINTER(hh_params), _P, _P, _P, ctypes.c_size_t, _P]),
+    "hh_covariance_noalloc": (ctypes.c_int32, [ctypes.POINTER(hh_params), _P, _P, _P]),
+    "hh_covariance_noalloc_max_bytes": (ctypes.c_size_t, []),
     "hh_eigh": (ctypes.c_int32, [ctypes.c_int32, _P, _P, _P, _P, _P]),
     "hh_eigh_ex": (ctypes.c_int32, [ctypes.c_int32, _P, _P, _P, _P, ctypes.c_int32, _P]),
     "hh_eigh_tridiag": (ctypes.c_int32, [ctypes.c_int32, _P, _P, _P, _P, ctypes.c_int32, _P]),
@@ -197,6 +199,20 @@ def hh_covariance(p: Params, holo, cov, workspace, stream=None):
     _check(lib().hh_covariance(ctypes.byref(p.c()), _ptr(holo), _ptr(cov), _ptr(workspace),
                                workspace.numel() * workspace.element_size(), _stream(stream)))
     return cov
+
+
+def hh_covariance_noalloc(p: Params, holo, cov, stream=None):
+    """hh_covariance with its partials in the library's static device scratch (no
+    workspace, no device allocation); calls on one GPU must not overlap."""
+    import torch
+    _dev_tensor(holo, torch.complex64, (p.nt, p.ny, p.nx), "holo")
+    _dev_tensor(cov, torch.complex128, (p.nt, p.nt), "cov")
+    _check(lib().hh_covariance_noalloc(ctypes.byref(p.c()), _ptr(holo), _ptr(cov), _stream(stream)))
+    return cov
+
+
+def covariance_noalloc_max_bytes() -> int:
+    return int(lib().hh_covariance_noalloc_max_bytes())
 
 
 def hh_covariance_frames(p: Params, frames, cov, workspace, stream=None):
