@@ -92,7 +92,8 @@ def algorithmic_bytes(kernel: str, launches_per_step: int) -> float:
 # or by timing the candidate shapes with --tuning, and pinned so that runs are
 # reproducible and comparable with the counter runs below; --autotune reruns the
 # tuner instead.
-PINNED_TUNING = {"fp32": "8,7,512,32,1", "fp16store": "8,7,256,16,0", "exact": "8,7,1024,16,0",
+PINNED_TUNING = {"fp32": "8,7,512,32,1,0", "fp32fused": "8,7,512,32,1,1", "fp16store": "8,7,256,16,0",
+                 "exact": "8,7,1024,16,0",
                  "bf16": "8,7,256,32,0", "bf16x3": "8,7,256,32,0", "fp16": "8,7,256,32,0", "fp16x3": "8,7,256,32,0",
                  "fp8e4m3": "8,7,256,32,0"}
 
@@ -102,14 +103,14 @@ PINNED_TUNING = {"fp32": "8,7,512,32,1", "fp16store": "8,7,256,16,0", "exact": "
 # the pinned launch choices; anything else reports null.
 MEASURED_TRAFFIC = {
     "fingerprint": "cf85f115700ce3ea",
-    "fp32": {"tuning": "8,7,512,32,1", "bytes": {
+    "fp32": {"tuning": "8,7,512,32,1,0", "bytes": {
         "fresnel_cols": (259.8 + 268.0) * 2 ** 20, "fresnel_rows": (64.3 + 256.0) * 2 ** 20,
         "gram_partial": (257.1 + 8.3) * 2 ** 20, "project_complement": (256.0 + 4.0) * 2 ** 20}},
-    "fp16store": {"tuning": "8,7,256,16,0", "bytes": {
+    "fp16store": {"tuning": "8,7,256,16,0,0", "bytes": {
         "fresnel_cols_r16": (64.3 + 35.0) * 2 ** 20, "fresnel_rows": (20.3 + 64.0) * 2 ** 20,
         "gram_partial_r16": (142.6 + 16.5) * 2 ** 20, "project_r16_complement": (136.0 + 4.0) * 2 ** 20,
         "frame_mean": (64.0 + 4.0) * 2 ** 20}},
-    "exact+first": {"tuning": "8,7,1024,16,0", "bytes": {
+    "exact+first": {"tuning": "8,7,1024,16,0,0", "bytes": {
         "proj_rows": (64.8 + 240.0) * 2 ** 20, "cols_energy": (240.4 + 32.0) * 2 ** 20,
         "gram_partial_u16": (64.1 + 4.1) * 2 ** 20, "energy_sum": (32.0 + 4.0) * 2 ** 20}},
 }
@@ -117,7 +118,8 @@ MEASURED_TRAFFIC = {
 
 # sources of the kernels whose traffic is tabulated (the eigensolver and the host
 # API are not among them: launch choices are checked through the tuning string)
-TRAFFIC_SOURCES = ("fft_common.h", "hh_internal.h", "fresnel.hip", "gram.hip", "project.hip", "projfirst.hip")
+TRAFFIC_SOURCES = ("fft_common.h", "hh_internal.h", "fresnel.hip", "fresnel_pca.hip", "gram.hip", "project.hip",
+                   "projfirst.hip")
 
 
 def source_fingerprint() -> str:
@@ -245,7 +247,8 @@ def main():
     ap.add_argument("--autotune", action="store_true",
                     help="run the autotuner first (untimed) instead of the pinned launch choices")
     ap.add_argument("--tuning", default=None,
-                    help="launch choices 'rows,cols,pxw,group[,gram_ref]', e.g. 2,0,512,0 (default: the pinned ones)")
+                    help="launch choices 'rows,cols,pxw,group[,gram_ref[,fused]]', e.g. 2,0,512,0 (default: the pinned "
+                         "ones)")
     ap.add_argument("--workload", default="stack", choices=["stack", "batched8", "serve"],
                     help="stack: the 1024^2 x 32 headline; batched8: 8 uneven stacks replayed as one HIP graph; "
                          "serve: two simulated cameras through the streaming server")
@@ -295,7 +298,7 @@ def main():
         vals = [int(v) for v in (args.tuning or PINNED_TUNING.get(args.precision, "0,0,256,0")).split(",")]
         hh.tuning_set(p, *vals)
     tuning = hh.tuning_get(p)
-    tuning_str = ",".join(str(tuning[k]) for k in ("fft_rows", "fft_cols", "gram_pxw", "group", "gram_ref"))
+    tuning_str = ",".join(str(tuning[k]) for k in ("fft_rows", "fft_cols", "gram_pxw", "group", "gram_ref", "fused"))
     img1 = torch.empty((NY, NX), dtype=torch.float32, device=dev)
     info = torch.empty(1, dtype=torch.int32, device=dev)
     S = max(1, args.streams) if B > 1 else 1

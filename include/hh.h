@@ -375,11 +375,22 @@ void hh_graph_destroy(hh_graph *g);
  *   group    : frames per Fresnel group (row pass then column pass), 0 = about
  *              64 MiB of FP32 holograms, at most four times that (the FP16
  *              storage form clamps it to the default, the size of its buffer).
- * The FFT choices and the group apply to every call with the same (nx, ny) on
- * the current device, gram_pxw and gram_ref to the same (nx * ny, nt, precision).
+ *   fused    : HH_FP32 form of the entry points that start from frames: 1 = three
+ *              passes over one hologram-sized buffer where the shape allows it
+ *              (nx in {512, 1024, 2048}, ny in {512, 1024}, nt <= 32): the column
+ *              transforms with one radix-4 split of the row transform, then the
+ *              remaining quarter-row transforms of every frame finished in LDS and
+ *              fed to the covariance, and after step (c) the same transforms fed to
+ *              the projection, so H is never stored (HBM traffic: the frames once,
+ *              one hologram-sized buffer written once and read twice, the image);
+ *              0 (the default) = the row pass, column pass, covariance and
+ *              projection on a stored H (the only form elsewhere).  The other
+ *              choices above apply to the stored-H form.
+ * The FFT choices, the group and fused apply to every call with the same (nx, ny)
+ * on the current device, gram_pxw and gram_ref to the same (nx * ny, nt, precision).
  */
 typedef struct {
-  int32_t fft_rows, fft_cols, gram_pxw, group, gram_ref;
+  int32_t fft_rows, fft_cols, gram_pxw, group, gram_ref, fused;
 } hh_tuning;
 
 /* Choices now in force for *p (defaults where none were set).  Uses nx, ny, nt, precision. */

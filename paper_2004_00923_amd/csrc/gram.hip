@@ -1014,6 +1014,11 @@ hipError_t gram_tail(const GramLayout &L, int nt, double *partial, double *parti
                      bool finalize);
 }
 
+hipError_t launch_gram_tail(const GramLayout &L, int nt, double *partial, double *partial2, double *cov,
+                            hipStream_t s, bool finalize) {
+  return gram_tail(L, nt, partial, partial2, cov, s, finalize);
+}
+
 hipError_t launch_gram(const GramLayout &L, const float2 *holo, int nt, long long npix, double *partial,
                        double *partial2, double *cov, hipStream_t s, int precision, bool finalize) {
   if (precision != HH_FP32 && nt <= 32) {

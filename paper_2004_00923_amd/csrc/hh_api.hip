@@ -286,6 +286,7 @@ hh_status check_tune(const hh_params &p, const hh_tuning &t) {
   if (t.gram_pxw != 256 && t.gram_pxw != 512 && t.gram_pxw != 1024)
     return fail(HH_E_INVALID, "gram_pxw=%d: must be 256, 512 or 1024", t.gram_pxw);
   if (t.gram_ref < 0 || t.gram_ref > 1) return fail(HH_E_INVALID, "gram_ref=%d: must be 0 or 1", t.gram_ref);
+  if (t.fused < 0 || t.fused > 1) return fail(HH_E_INVALID, "fused=%d: must be 0 or 1", t.fused);
   if (t.group < 0 || t.group > 4 * default_group(p))
     return fail(HH_E_INVALID, "group=%d: must be in [0, %d] (0 = default)", t.group, 4 * default_group(p));
   return HH_OK;
@@ -342,6 +343,7 @@ float r16_inv_scale(long long npix) {
 // on the caller's hologram (holo given).  Fills the views that steps (d)+(e) read.
 struct StackViews {
   const float2 *H = nullptr;
+  const float2 *T = nullptr;  // three-pass FP32 form: the column-transformed frames (not H)
   const h2 *r16 = nullptr;
   const float2 *m = nullptr;
   float inv_s = 1.f;
@@ -384,6 +386,19 @@ hipError_t enqueue_front(const hh_params &p, const Plan *pl, const PipeLayout &L
     v.pl = pl;
     return launch_gram_u16(gl, frames, p.nt, npix, part, part2, v.cov, s, false);
   }
+  if (frames && p.precision == HH_FP32 && tu.fused && fused_supported(p.nx, p.ny, p.nt)) {
+    float2 *Tb = reinterpret_cast<float2 *>(ws + L.holo);
+    int groups = 0;
+    hipError_t e = launch_fused_front(*pl, frames, p.nt, Tb, L.g.groups, part, &groups, s);
+    if (e != hipSuccess) return e;
+    GramLayout fl = gl;
+    fl.groups = groups;
+    fl.groups2 = groups < fl.groups2 ? groups : fl.groups2;
+    v.T = Tb;
+    v.pl = pl;
+    v.g2 = fl.groups2;
+    return launch_gram_tail(fl, p.nt, part, part2, v.cov, s, false);
+  }
   if (frames) {
     float2 *H = reinterpret_cast<float2 *>(ws + L.holo);
     hipError_t e = launch_fresnel(*pl, tu, frames, p.nt, H, s);
@@ -398,6 +413,7 @@ hipError_t enqueue_front(const hh_params &p, const Plan *pl, const PipeLayout &L
 
 hipError_t enqueue_back(const hh_params &p, const StackViews &v, const double *V, float *image, hipStream_t s) {
   const long long npix = (long long)p.nx * p.ny;
+  if (v.T) return launch_fused_back(*v.pl, v.T, p.nt, V, p.k_lo, p.k_hi, p.proj_mode, image, s);
   // C = N_pix I^T I is real symmetric, so the solver's eigenvectors are real: Re V suffices
   if (v.inter)
     return launch_project_frames(*v.pl, v.frames, p.nt, V, p.k_lo, p.k_hi, true, v.inter, v.eparts, image, s);
@@ -866,7 +882,7 @@ hh_status hh_tuning_get(const hh_params *p, hh_tuning *t) {
   hh_status st;
   if ((st = check_shape(p))) return st;
   const Tune tu = get_tune(*p);
-  *t = hh_tuning{tu.rows, tu.cols, tu.pxw, tu.group, tu.gram_ref};
+  *t = hh_tuning{tu.rows, tu.cols, tu.pxw, tu.group, tu.gram_ref, tu.fused};
   return HH_OK;
 }
 
@@ -874,7 +890,7 @@ hh_status hh_tuning_set(const hh_params *p, const hh_tuning *t) {
   if (!p || !t) return fail(HH_E_INVALID, "params and tuning must be non-NULL");
   hh_status st;
   if ((st = check_shape(p)) || (st = check_tune(*p, *t))) return st;
-  put_tune(*p, Tune{t->fft_rows, t->fft_cols, t->gram_pxw, t->group, t->gram_ref});
+  put_tune(*p, Tune{t->fft_rows, t->fft_cols, t->gram_pxw, t->group, t->gram_ref, t->fused});
   return HH_OK;
 }
 
@@ -934,7 +950,8 @@ hh_status hh_autotune(const hh_params *p, const uint16_t *frames, void *workspac
       {&Tune::cols, p->ny >= 512 ? std::vector<int>{0, 1, 2, 3, 4, 5, 6, 7} : std::vector<int>{0}},
       {&Tune::group, {0, std::max(1, dg / 2), std::max(1, dg / 4), std::min(2 * dg, p->nt), std::min(4 * dg, p->nt)}},
       {&Tune::pxw, {256, 512, 1024}},
-      {&Tune::gram_ref, {0, 1}}};
+      {&Tune::gram_ref, {0, 1}},
+      {&Tune::fused, {1, 0}}};
   for (auto &ax : axes) {
     for (int val : ax.second) {
       if (st != HH_OK) break;
@@ -953,7 +970,7 @@ hh_status hh_autotune(const hh_params *p, const uint16_t *frames, void *workspac
   if (img) (void)hipFree(img);
   if (ev0) (void)hipEventDestroy(ev0);
   if (ev1) (void)hipEventDestroy(ev1);
-  if (st == HH_OK && best) *best = hh_tuning{cur.rows, cur.cols, cur.pxw, cur.group, cur.gram_ref};
+  if (st == HH_OK && best) *best = hh_tuning{cur.rows, cur.cols, cur.pxw, cur.group, cur.gram_ref, cur.fused};
   return st;
 }
 

@@ -75,6 +75,7 @@ struct Tune {
   int pxw = 256;     // Gram pixels per wave: 256, 512 or 1024
   int group = 0;     // frames per Fresnel group, 0 = about 64 MiB of holograms
   int gram_ref = 0;  // reference of the covariance's mean split (FP32 form): 0 temporal mean, 1 frame 0
+  int fused = 0;     // FP32 pipeline: 1 = the three-pass form (fresnel_pca.hip) where the shape allows it
 };
 constexpr int kGramPxwMin = 256;  // the workspace is sized for the smallest split-K chunk
 GramLayout gram_layout(int nt, long long npix, int pxw = kGramPxwMin);
@@ -84,12 +85,27 @@ GramLayout gram_layout(int nt, long long npix, int pxw = kGramPxwMin);
 hipError_t launch_gram(const GramLayout &L, const float2 *holo, int nt, long long npix,
                        double *partial, double *partial2, double *cov, hipStream_t s, int precision = HH_FP32,
                        bool finalize = true);
+// Second half of launch_gram: fixed-order reduction of L.groups partials into
+// L.groups2, then (finalize) the Hermitian assembly into cov.
+hipError_t launch_gram_tail(const GramLayout &L, int nt, double *partial, double *partial2, double *cov,
+                            hipStream_t s, bool finalize);
 // Exact covariance from the frames, C = N_pix I^T I (n_t <= 64; frames 16-byte aligned).
 hipError_t launch_gram_u16(const GramLayout &L, const uint16_t *frames, int nt, long long npix, double *partial,
                            double *partial2, double *cov, hipStream_t s, bool finalize = true);
 // FP16 storage form: H = m 1^T + r16 / s with inv_s = 1 / s (n_t <= 32).
 hipError_t launch_gram_r16(const GramLayout &L, const h2 *r16, const float2 *m, int nt, long long npix, float inv_s,
                            double *partial, double *partial2, double *cov, hipStream_t s, bool finalize = true);
+
+// Steps (a)-(e) of the FP32 form in three passes (fresnel_pca.hip): the column
+// transform with a radix-4 split of the rows into tbuf (complex64, the size of
+// the holograms), then the quarter-row transforms with the covariance partials
+// (*groups partials, at most max_groups); after the eigensolver, the same
+// transforms with the projection and |.|^2.  Shapes: fused_supported.
+bool fused_supported(int nx, int ny, int nt);
+hipError_t launch_fused_front(const Plan &pl, const uint16_t *frames, int nt, float2 *tbuf, int max_groups,
+                              double *partial, int *groups, hipStream_t s);
+hipError_t launch_fused_back(const Plan &pl, const float2 *tbuf, int nt, const double *V, int k_lo, int k_hi,
+                             int mode, float *image, hipStream_t s);
 
 // Step (c): one workgroup per problem; problems are passed by value (kernel argument).
 // One eigenproblem.  Either cov holds C (complex128 [n][n]), or part2 holds the

@@ -73,7 +73,7 @@ class hh_window(ctypes.Structure):
 
 class hh_tuning(ctypes.Structure):
     _fields_ = [("fft_rows", ctypes.c_int32), ("fft_cols", ctypes.c_int32), ("gram_pxw", ctypes.c_int32),
-                ("group", ctypes.c_int32), ("gram_ref", ctypes.c_int32)]
+                ("group", ctypes.c_int32), ("gram_ref", ctypes.c_int32), ("fused", ctypes.c_int32)]
 
     def as_dict(self):
         return {f: int(getattr(self, f)) for f, _ in self._fields_}
@@ -423,8 +423,8 @@ def tuning_get(p: Params) -> dict:
     return t.as_dict()
 
 
-def tuning_set(p: Params, fft_rows=0, fft_cols=0, gram_pxw=256, group=0, gram_ref=0):
-    t = hh_tuning(fft_rows, fft_cols, gram_pxw, group, gram_ref)
+def tuning_set(p: Params, fft_rows=0, fft_cols=0, gram_pxw=256, group=0, gram_ref=0, fused=0):
+    t = hh_tuning(fft_rows, fft_cols, gram_pxw, group, gram_ref, fused)
     _check(lib().hh_tuning_set(ctypes.byref(p.c()), ctypes.byref(t)))
 
 

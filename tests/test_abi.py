@@ -197,13 +197,16 @@ def test_status_strings():
 def test_tuning_validation_and_roundtrip():
     hh.tuning_reset()
     p = hh.Params(nx=1024, ny=1024, nt=32, k_lo=2, k_hi=31)
-    assert hh.tuning_get(p) == {"fft_rows": 0, "fft_cols": 0, "gram_pxw": 256, "group": 0, "gram_ref": 0}
-    hh.tuning_set(p, fft_rows=1, fft_cols=2, gram_pxw=1024, group=4, gram_ref=1)
-    assert hh.tuning_get(p) == {"fft_rows": 1, "fft_cols": 2, "gram_pxw": 1024, "group": 4, "gram_ref": 1}
+    assert hh.tuning_get(p) == {"fft_rows": 0, "fft_cols": 0, "gram_pxw": 256, "group": 0, "gram_ref": 0,
+                                "fused": 0}
+    hh.tuning_set(p, fft_rows=1, fft_cols=2, gram_pxw=1024, group=4, gram_ref=1, fused=1)
+    assert hh.tuning_get(p) == {"fft_rows": 1, "fft_cols": 2, "gram_pxw": 1024, "group": 4, "gram_ref": 1,
+                                "fused": 1}
     # FFT choices follow (nx, ny); the split-K chunk follows (nx * ny, nt, precision)
     q = hh.Params(nx=1024, ny=1024, nt=16, k_lo=2, k_hi=15)
     assert hh.tuning_get(q)["fft_rows"] == 1 and hh.tuning_get(q)["gram_pxw"] == 256
-    for bad in ({"fft_rows": 10}, {"fft_cols": 8}, {"gram_pxw": 300}, {"group": -1}, {"group": 33}, {"gram_ref": 2}):
+    for bad in ({"fft_rows": 10}, {"fft_cols": 8}, {"gram_pxw": 300}, {"group": -1}, {"group": 33}, {"gram_ref": 2},
+                {"fused": 2}, {"fused": -1}):
         with pytest.raises(hh.HHError) as ei:
             hh.tuning_set(p, **bad)
         assert ei.value.status == hh.HH_E_INVALID

@@ -51,7 +51,8 @@ def case(hh):
 def test_every_launch_choice_meets_the_bar(hh, case, rows, cols, pxw, group, precision, gram_ref):
     f, fd, ref = case
     p = hh.Params(nx=1024, ny=512, nt=32, k_lo=2, k_hi=31, precision=hh.PRECISIONS[precision])
-    hh.tuning_set(p, fft_rows=rows, fft_cols=cols, gram_pxw=pxw, group=group, gram_ref=gram_ref)
+    # the row/column/covariance kernels on stored holograms (fused=0)
+    hh.tuning_set(p, fft_rows=rows, fft_cols=cols, gram_pxw=pxw, group=group, gram_ref=gram_ref, fused=0)
     try:
         e = rel(_run(hh, p, fd), ref)
     finally:
@@ -99,7 +100,7 @@ def test_persistent_and_capped_shapes_at_other_lengths(hh, ny, nx, rows, cols):
     f = gen_stack(ny + nx + rows, 8, ny, nx)
     r = oracle.pipeline_ref(f, LAM, Z, PITCH, 1, 7)
     p = hh.Params(nx=nx, ny=ny, nt=8, k_lo=1, k_hi=7)
-    hh.tuning_set(p, fft_rows=rows, fft_cols=cols)
+    hh.tuning_set(p, fft_rows=rows, fft_cols=cols, fused=0)
     try:
         e = rel(_run(hh, p, to_dev(f)), r["image"])
     finally:
