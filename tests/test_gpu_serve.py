@@ -124,9 +124,90 @@ def test_serve_admission_rejects_over_budget(hh):
     from paper_2004_00923_amd.serve import AdmissionError, CameraSpec, RingPlan, Server, camera_bytes
     A = CameraSpec("A", 128, 128, 500.0, 100)
     B = CameraSpec("B", 128, 256, 250.0, 101)
-    need_a = sum(camera_bytes(A, RingPlan(32, 25), 4).values())
+    need_a = sum(camera_bytes(A, A.ring(), 4).values())
     srv = Server(hbm_budget_bytes=need_a + 1024)
     srv.admit(A, torch.zeros((4, 128, 128), dtype=torch.uint16, pin_memory=True))
     with pytest.raises(AdmissionError):
         srv.admit(B, torch.zeros((4, 128, 256), dtype=torch.uint16, pin_memory=True))
     assert len(srv.cams) == 1
+
+
+def test_serve_alone_vs_mix_at_camera_sizes(hh):
+    # camera A (1024^2, 500 frames/s) alone and mixed with camera B (2048 x 1024,
+    # 250 frames/s), paced: A's images are bit-identical in both runs, and one window
+    # of each camera matches the oracle at full size
+    from paper_2004_00923_amd.serve import CameraSpec
+    A = CameraSpec("A", 1024, 1024, 500.0, 100)
+    B = CameraSpec("B", 1024, 2048, 250.0, 101)
+    n_src = 57
+    src = {"A": _source(A.seed, n_src, A.ny, A.nx), "B": _source(B.seed, n_src, B.ny, B.nx)}
+    wa, wb = 3, 2
+    keepA = [("A", c) for c in range(wa)]
+    keepB = [("B", c) for c in range(wb)]
+    say("serve 1024^2 alone, paced")
+    alone, _ = _serve([A], src, {"A": wa}, True, keepA)
+    say("serve 1024^2 + 2048x1024, paced")
+    mix, res = _serve([A, B], src, {"A": wa, "B": wb}, True, keepA + keepB)
+    assert len(res["windows"]) == wa + wb
+    for c in range(wa):
+        assert np.array_equal(to_np(alone.kept[("A", c)]), to_np(mix.kept[("A", c)])), f"A window {c}"
+    for name, spec, c in (("A", A, 1), ("B", B, 1)):
+        frames = src[name][0]
+        idx = [(c * spec.hop + j) % n_src for j in range(spec.window)]
+        r = oracle.pipeline_ref(frames[idx], LAM, Z, PITCH, 2, 31)
+        e = rel(to_np(mix.kept[(name, c)]), r["image"])
+        say(f"  {name} window {c} vs oracle: {e:.2e}")
+        assert e <= IMG_TOL
+
+
+def test_serve_queued_camera_admitted_when_memory_frees(hh):
+    # the budget holds one camera: B is requested with A but waits until A has
+    # produced its windows and released its memory, then joins; both are correct
+    from paper_2004_00923_amd.serve import CameraRequest, CameraSpec, RingPlan, Server, camera_bytes
+    A = CameraSpec("A", 128, 128, 500.0, 100)
+    B = CameraSpec("B", 128, 256, 500.0, 101)
+    n_src = 48
+    src = {"A": _source(A.seed, n_src, A.ny, A.nx), "B": _source(B.seed, n_src, B.ny, B.nx)}
+    need_b = sum(camera_bytes(B, B.ring(), 4).values())
+    srv = Server(hbm_budget_bytes=need_b + 1024)
+    srv.submit(CameraRequest(A, src["A"][1], windows=3))
+    srv.submit(CameraRequest(B, src["B"][1], windows=2, at_s=0.01))
+    srv.keep_windows = {("A", c) for c in range(3)} | {("B", c) for c in range(2)}
+    res = srv.run(paced=True)
+    say(f"queued admission: waits {res['admission_wait_s']} cameras {res['cameras']}")
+    assert res["cameras"]["A"]["analysed"] == 3 and res["cameras"]["B"]["analysed"] == 2
+    assert res["cameras"]["B"]["admitted_s"] >= res["cameras"]["A"]["released_s"]
+    assert res["admission_wait_s"]["B"] > 0
+    assert srv.adm.used == 0 and not srv.cams
+    for name, spec, nw in (("A", A, 3), ("B", B, 2)):
+        frames = src[name][0]
+        for c in range(nw):
+            idx = [(c * spec.hop + j) % n_src for j in range(spec.window)]
+            r = oracle.pipeline_ref(frames[idx], LAM, Z, PITCH, 2, 31)
+            assert rel(to_np(srv.kept[(name, c)]), r["image"]) <= IMG_TOL, f"{name} window {c}"
+
+
+def test_serve_gaps_and_disconnect(hh):
+    # camera A skips sequence numbers 30 and 31 (windows 0 and 1 hold them); camera B
+    # disconnects early: its remaining windows are abandoned and its memory released
+    from paper_2004_00923_amd.serve import CameraRequest, CameraSpec, Server
+    A = CameraSpec("A", 128, 128, 500.0, 100)
+    B = CameraSpec("B", 128, 128, 500.0, 102)
+    n_src = 48
+    src = {"A": _source(A.seed, n_src, A.ny, A.nx), "B": _source(B.seed, n_src, B.ny, B.nx)}
+    srv = Server(hbm_budget_bytes=8 << 30)
+    srv.submit(CameraRequest(A, src["A"][1], windows=5, missing=frozenset({30, 31})))
+    srv.submit(CameraRequest(B, src["B"][1], windows=50, disconnect_s=0.15))
+    srv.keep_windows = {("A", c) for c in range(5)}
+    res = srv.run(paced=True)
+    ca, cb = res["cameras"]["A"], res["cameras"]["B"]
+    say(f"gaps/disconnect: A {ca} B {cb}")
+    assert ca["gap_frames"] == 2 and ca["skipped"] == 2 and ca["analysed"] == 3
+    assert set(c for n, c in srv.kept if n == "A") == {2, 3, 4}
+    assert cb["abandoned"] > 0 and cb["analysed"] + cb["abandoned"] + cb["skipped"] <= 50
+    assert srv.adm.used == 0
+    frames = src["A"][0]
+    for c in (2, 3, 4):
+        idx = [(c * A.hop + j) % n_src for j in range(A.window)]
+        r = oracle.pipeline_ref(frames[idx], LAM, Z, PITCH, 2, 31)
+        assert rel(to_np(srv.kept[("A", c)]), r["image"]) <= IMG_TOL
