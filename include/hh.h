@@ -76,8 +76,12 @@ enum {
  * has unit modulus and the unnormalised DFT satisfies F^H F = nx ny I, so C of
  * Eq. (4) equals nx ny I^T I for the real interferogram matrix I, an integer Gram
  * evaluated exactly in FP64 (same entry points as HH_FP16_STORE).  Forms 1-6
- * require nt <= 32 (else HH_E_UNSUPPORTED).  The projection is FP32/FP64 in
- * every form. */
+ * require nt <= 32 (else HH_E_UNSUPPORTED).  Forms 1-5 also run the projection
+ * of Eqs. (6)-(7) on MFMA in their operand format (unless proj_mode is
+ * HH_PROJ_COMPLEMENT): the kept components as one real product per 16 pixels,
+ * z = m s + r V with m the pixel's temporal mean (FP32) and only the residual r
+ * rounded (a power-of-two scale per pixel for FP16 and FP8), FP32 accumulation,
+ * |z|^2 summed in FP32.  The other forms project in FP32/FP64. */
 enum {
   HH_FP32 = 0,      /* FP32 operands, FP32 sums of <= 512 products, FP64 reduction */
   HH_BF16 = 1,      /* BF16 operands (round to nearest even) on MFMA, FP32 accumulation */
@@ -238,7 +242,10 @@ hh_status hh_eigh_tridiag(int32_t nt, const double *cov, double *evals, double *
  *   evecs : complex128 [nt][nt], evecs[t][k] = V[t][k] (as written by hh_eigh).
  *   image : float32 [ny][nx] output, M[p] = sum_{k=k_lo..k_hi} |sum_t H[p][t] V[t][k]|^2.
  * Uses nx, ny, nt, k_lo, k_hi, precision, proj_mode of *p.  HH_PROJ_COMPLEMENT
- * and HH_PROJ_AUTO rely on V being unitary (as hh_eigh returns it).
+ * and HH_PROJ_AUTO rely on V being unitary (as hh_eigh returns it).  With
+ * precision HH_BF16 .. HH_FP8E4M3 (nt <= 32) and proj_mode other than
+ * HH_PROJ_COMPLEMENT, the kept components are projected on MFMA in that format
+ * (see the precision forms above).
  */
 hh_status hh_project_render(const hh_params *p, const float *holo, const double *evecs,
                             float *image, void *stream);

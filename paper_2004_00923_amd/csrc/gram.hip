@@ -361,12 +361,6 @@ enum { kLpBF16 = 0, kLpFP16 = 1, kLpFP8 = 2 };
 typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 typedef _Float16 v8h __attribute__((ext_vector_type(8)));
 
-__device__ __forceinline__ unsigned short bf16_bits(float x) {  // round to nearest even
-  unsigned u = __float_as_uint(x);
-  u += 0x7FFFu + ((u >> 16) & 1u);
-  return (unsigned short)(u >> 16);
-}
-__device__ __forceinline__ float bf16_val(unsigned short b) { return __uint_as_float((unsigned)b << 16); }
 
 template <int FMT>
 struct LpOp;
@@ -375,12 +369,13 @@ struct LpOp<kLpBF16> {
   typedef v8bf vec;
   union U {
     vec v;
-    unsigned short s[8];
+    __bf16 s[8];
   };
+  // hardware round to nearest even (v_cvt_pk_bf16_f32)
   __device__ static float put(U &u, int e, float x) {
-    const unsigned short b = bf16_bits(x);
+    const __bf16 b = (__bf16)x;
     u.s[e] = b;
-    return bf16_val(b);
+    return (float)b;
   }
   __device__ static v4f mma(const vec &a, const vec &b, v4f c) { return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0); }
 };

@@ -418,7 +418,7 @@ hipError_t enqueue_back(const hh_params &p, const StackViews &v, const double *V
   if (v.inter)
     return launch_project_frames(*v.pl, v.frames, p.nt, V, p.k_lo, p.k_hi, true, v.inter, v.eparts, image, s);
   if (v.r16) return launch_project_r16(v.r16, v.m, v.inv_s, p.nt, npix, V, p.k_lo, p.k_hi, p.proj_mode, image, s);
-  return launch_project(v.H, p.nt, npix, V, p.k_lo, p.k_hi, p.proj_mode, image, s);
+  return launch_project(v.H, p.nt, npix, V, p.k_lo, p.k_hi, p.proj_mode, image, s, p.precision);
 }
 
 constexpr int kMaxBatch = 4096;
@@ -694,7 +694,7 @@ hh_status hh_project_render(const hh_params *p, const float *holo, const double 
   if (!aligned(holo, 16) || !aligned(evecs, 16) || !aligned(image, 8))
     return fail(HH_E_INVALID, "holo/evecs/image misaligned");
   hipError_t e = launch_project(reinterpret_cast<const float2 *>(holo), p->nt, (long long)p->nx * p->ny, evecs,
-                                p->k_lo, p->k_hi, p->proj_mode, image, (hipStream_t)stream);
+                                p->k_lo, p->k_hi, p->proj_mode, image, (hipStream_t)stream, p->precision);
   if (e != hipSuccess) return device_fail(e, "hh_project_render");
   return HH_OK;
 }

@@ -131,8 +131,11 @@ hipError_t launch_eigh(int nt, const double *cov, double *evals, double *evecs, 
 hipError_t launch_eigh_batch(const EighProblem *probs, int count, int max_iter, hipStream_t s);
 
 // Steps (d)+(e)
+// precision: HH_FP32 (and the forms that store H differently) project in FP32/FP64;
+// the forms HH_BF16 .. HH_FP8E4M3 (nt <= 32) project the kept components on MFMA in
+// their operand format unless mode is HH_PROJ_COMPLEMENT.
 hipError_t launch_project(const float2 *holo, int nt, long long npix, const double *V, int k_lo,
-                          int k_hi, int mode, float *image, hipStream_t s);
+                          int k_hi, int mode, float *image, hipStream_t s, int precision = HH_FP32);
 // FP16 storage form of steps (d)+(e): H = m + r16 * inv_s
 hipError_t launch_project_r16(const h2 *r16, const float2 *m, float inv_s, int nt, long long npix, const double *V,
                               int k_lo, int k_hi, int mode, float *image, hipStream_t s);

@@ -204,6 +204,237 @@ hipError_t launch_filter(int kcount, const float4 *H, int nt, long long npair, c
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// The direct projection on MFMA (precision forms): M[p] = sum over kept k of
+// |z_k|^2 with z = h V restated as a real product.  Each pixel is split as
+// h = m + r, m its temporal mean (FP32), so z_k = m s_k + sum_t r_t V[t][k] with
+// s_k = sum_t V[t][k]: only r (a few per cent of h) goes through the low-precision
+// format, m s_k is added in FP32.  With c = 2a + part (a = position in the kept
+// list, part 0/1 = real/imaginary) and kk = 2t + part' (frame t),
+//   Z[c][p] = sum_kk A[c][kk] B[kk][p],  A = [[Re V, -Im V], [Im V, Re V]] per (a, t),
+//   B[2t][p] = Re r_t(p), B[2t+1][p] = Im r_t(p),
+// a 64 x 64 by 64 x 16 product per 16 pixels on v_mfma_f32_16x16x32_{bf16,f16} or
+// _fp8_fp8 (4 row tiles x 2 k-steps), with FP32 accumulation.  A (from V, a
+// 64 x 64 matrix shared by every pixel) is always kept as hi + lo and both parts
+// are multiplied with B (two products); SPLIT also splits B (the streamed
+// residual) and adds the hi*lo' product (three).  B is scaled per pixel by a power of two (FP16, FP8)
+// so that its largest entry fits the format, and A by 2^8 for FP8 (|V| <= 1); the
+// scales are undone exactly in the epilogue.  One wave takes 16 pixels at a time:
+// lane (n, g), n = lane % 16 the pixel, g = lane / 16 the k-block, holds frames
+// 16 j + 4 g .. + 3 of k-step j (8 values: re, im of four frames).
+enum { kPjBF16 = 0, kPjFP16 = 1, kPjFP8 = 2 };
+
+typedef __bf16 pv8bf __attribute__((ext_vector_type(8)));
+typedef _Float16 pv8h __attribute__((ext_vector_type(8)));
+typedef float pv4f __attribute__((ext_vector_type(4)));
+
+template <int FMT>
+struct PjOp;
+template <>
+struct PjOp<kPjBF16> {
+  typedef pv8bf vec;
+  typedef __bf16 elt;
+  static constexpr float kLim = 0.f;  // no scale
+  __device__ static elt cvt(float x) { return (__bf16)x; }
+  __device__ static float back(elt x) { return (float)x; }
+  __device__ static pv4f mma(const vec &a, const vec &b, pv4f c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+  }
+};
+template <>
+struct PjOp<kPjFP16> {
+  typedef pv8h vec;
+  typedef _Float16 elt;
+  static constexpr float kLim = 16384.f;  // headroom for the lo residual and the sums
+  __device__ static elt cvt(float x) { return (_Float16)x; }
+  __device__ static float back(elt x) { return (float)x; }
+  __device__ static pv4f mma(const vec &a, const vec &b, pv4f c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
+  }
+};
+template <>
+struct PjOp<kPjFP8> {
+  typedef long vec;
+  typedef unsigned char elt;
+  static constexpr float kLim = 448.f;  // OCP e4m3 maximum
+  __device__ static elt cvt(float x) { return (unsigned char)(__builtin_amdgcn_cvt_pk_fp8_f32(x, 0.f, 0, false) & 0xFF); }
+  __device__ static float back(elt x) { return __builtin_amdgcn_cvt_f32_fp8((int)x, 0); }
+  __device__ static pv4f mma(const vec &a, const vec &b, pv4f c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(a, b, c, 0, 0, 0);
+  }
+};
+
+template <int FMT, bool SPLIT>
+__global__ __launch_bounds__(256) void project_mfma(const float2 *__restrict__ H, int nt, long long npix,
+                                                    const double2 *__restrict__ V, KList kl,
+                                                    float *__restrict__ image) {
+  typedef PjOp<FMT> Op;
+  typedef typename Op::elt elt;
+  union Frag {
+    typename Op::vec v;
+    elt e[8];
+  };
+  constexpr float kAScale = FMT == kPjFP8 ? 256.f : 1.f;
+  __shared__ elt Ahi[64 * 64], Alo[64 * 64];
+  __shared__ float2 ssum[32];
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int n = lane & 15, g = lane >> 4;
+  const float inv_nt = 1.f / (float)nt;
+  // A (rows c = 2a + part, columns kk = 2t + part'), hi and lo parts
+  for (int i = tid; i < 64 * 64; i += 256) {
+    const int c = i >> 6, kk = i & 63, a = c >> 1, t = kk >> 1;
+    float x = 0.f;
+    if (a < kl.n && t < nt) {
+      const double2 v = V[t * nt + kl.k[a]];
+      const int pp = ((c & 1) << 1) | (kk & 1);
+      x = (float)(pp == 0 ? v.x : pp == 1 ? -v.y : pp == 2 ? v.y : v.x) * kAScale;
+    }
+    const elt h = Op::cvt(x);
+    Ahi[i] = h;
+    Alo[i] = Op::cvt(x - Op::back(h));
+  }
+  if (tid < 32) {
+    double sr = 0.0, si = 0.0;
+    if (tid < kl.n)
+      for (int t = 0; t < nt; ++t) {
+        const double2 v = V[t * nt + kl.k[tid]];
+        sr += v.x;
+        si += v.y;
+      }
+    ssum[tid] = make_float2((float)sr, (float)si);
+  }
+  __syncthreads();
+  Frag ah[4][2], al[4][2];
+#pragma unroll
+  for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int base = (16 * rt + n) * 64 + 32 * j + 8 * g;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        ah[rt][j].e[e] = Ahi[base + e];
+        al[rt][j].e[e] = Alo[base + e];
+      }
+    }
+  // this lane's components (rows 16 rt + 4 g + r): a = 8 rt + 2 g + r / 2
+  // each wave takes a contiguous range of tiles, so that its 32 frame streams are read
+  // sequentially (adjacent 128-byte lines from one tile to the next)
+  const long long tiles = (npix + 15) / 16;
+  const long long waves = (long long)gridDim.x * 4, per = (tiles + waves - 1) / waves;
+  const long long t_begin = ((long long)blockIdx.x * 4 + (tid >> 6)) * per;
+  const long long t_end = t_begin + per < tiles ? t_begin + per : tiles;
+  // the eight frames of this lane for one tile; the next tile's are loaded before
+  // this tile is converted and multiplied (unconditional loads from a valid address)
+  auto load = [&](long long tl, float2 (&d)[2][4]) {
+    const long long pc = tl < t_end && tl * 16 + n < npix ? tl * 16 + n : 0;
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int t = 16 * j + 4 * g + i;
+        d[j][i] = H[(long long)(t < nt ? t : 0) * npix + pc];
+      }
+  };
+  float2 nx_[2][4];
+  load(t_begin, nx_);
+  for (long long tile = t_begin; tile < t_end; ++tile) {
+    const long long p = tile * 16 + n;
+    const bool live = p < npix;
+    float2 h[2][4];
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) h[j][i] = nx_[j][i];
+    load(tile + 1, nx_);
+    // m: the pixel's temporal mean (the four lanes of the pixel hold eight frames each)
+    float mr = 0.f, mi = 0.f;
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+        if (16 * j + 4 * g + i < nt) {
+          mr += h[j][i].x;
+          mi += h[j][i].y;
+        }
+    mr += __shfl_xor(mr, 16);
+    mi += __shfl_xor(mi, 16);
+    mr += __shfl_xor(mr, 32);
+    mi += __shfl_xor(mi, 32);
+    mr *= inv_nt;
+    mi *= inv_nt;
+    float mx = 0.f;
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const bool on = 16 * j + 4 * g + i < nt;
+        h[j][i] = on ? make_float2(h[j][i].x - mr, h[j][i].y - mi) : make_float2(0.f, 0.f);
+        mx = fmaxf(mx, fmaxf(fabsf(h[j][i].x), fabsf(h[j][i].y)));
+      }
+    float sc = 1.f;
+    if constexpr (Op::kLim > 0.f) {
+      mx = fmaxf(mx, __shfl_xor(mx, 16));
+      mx = fmaxf(mx, __shfl_xor(mx, 32));
+      if (mx > 0.f) {
+        int ex;
+        frexpf(Op::kLim / mx, &ex);  // kLim / mx = f 2^ex, f in [0.5, 1)
+        sc = ldexpf(1.f, ex - 1);
+      }
+    }
+    Frag bh[2], bl[2];
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+          const float x = (q ? h[j][i].y : h[j][i].x) * sc;
+          const elt hi = Op::cvt(x);
+          bh[j].e[2 * i + q] = hi;
+          if constexpr (SPLIT) bl[j].e[2 * i + q] = Op::cvt(x - Op::back(hi));
+        }
+    pv4f acc[4];
+#pragma unroll
+    for (int rt = 0; rt < 4; ++rt) {
+      acc[rt] = pv4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        acc[rt] = Op::mma(ah[rt][j].v, bh[j].v, acc[rt]);
+        acc[rt] = Op::mma(al[rt][j].v, bh[j].v, acc[rt]);
+        if constexpr (SPLIT) acc[rt] = Op::mma(ah[rt][j].v, bl[j].v, acc[rt]);
+      }
+    }
+    const float inv = 1.f / (sc * kAScale);  // powers of two: exact
+    float e = 0.f;
+#pragma unroll
+    for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const int a = 8 * rt + 2 * g + u;
+        if (a < kl.n) {
+          const float2 s = ssum[a];
+          const float zr = acc[rt][2 * u] * inv + (mr * s.x - mi * s.y);
+          const float zi = acc[rt][2 * u + 1] * inv + (mr * s.y + mi * s.x);
+          e += zr * zr + zi * zi;
+        }
+      }
+    e += __shfl_xor(e, 16);
+    e += __shfl_xor(e, 32);
+    if (g == 0 && live) image[p] = e;
+  }
+}
+
+template <int FMT, bool SPLIT>
+hipError_t launch_pmfma(const float2 *H, int nt, long long npix, const double2 *V, const KList &kl, float *image,
+                        hipStream_t s) {
+  const long long tiles = (npix + 15) / 16;
+  long long groups = (tiles + 31) / 32;  // about eight tiles per wave
+  if (groups < 1) groups = 1;
+  if (groups > 4096) groups = 4096;
+  hipLaunchKernelGGL((project_mfma<FMT, SPLIT>), dim3((unsigned)groups), dim3(256), 0, s, H, nt, npix, V, kl, image);
+  return hipGetLastError();
+}
+
 // kept / dropped component lists of the selector I_f
 bool select_list(int nt, int k_lo, int k_hi, int mode, KList &kl) {
   const int kept = k_hi - k_lo + 1, dropped = nt - kept;
@@ -229,8 +460,21 @@ hipError_t launch_svd_filter(const float2 *holo, int nt, long long npix, const d
 }
 
 hipError_t launch_project(const float2 *holo, int nt, long long npix, const double *V, int k_lo, int k_hi,
-                          int mode, float *image, hipStream_t s) {
+                          int mode, float *image, hipStream_t s, int precision) {
   KList kl;
+  if (precision >= HH_BF16 && precision <= HH_FP8E4M3 && nt <= 32 && mode != HH_PROJ_COMPLEMENT) {
+    // precision forms: the kept components on MFMA in the form's operand format
+    select_list(nt, k_lo, k_hi, HH_PROJ_DIRECT, kl);
+    const double2 *V2 = reinterpret_cast<const double2 *>(V);
+    ProfScope ps("project_mfma", s);
+    switch (precision) {
+      case HH_BF16: return launch_pmfma<kPjBF16, false>(holo, nt, npix, V2, kl, image, s);
+      case HH_BF16X3: return launch_pmfma<kPjBF16, true>(holo, nt, npix, V2, kl, image, s);
+      case HH_FP16: return launch_pmfma<kPjFP16, false>(holo, nt, npix, V2, kl, image, s);
+      case HH_FP16X3: return launch_pmfma<kPjFP16, true>(holo, nt, npix, V2, kl, image, s);
+      default: return launch_pmfma<kPjFP8, false>(holo, nt, npix, V2, kl, image, s);
+    }
+  }
   const bool complement = select_list(nt, k_lo, k_hi, mode, kl);
   const long long npair = npix / 2;
   const LoadF32 H{reinterpret_cast<const float4 *>(holo), npair};
