@@ -442,11 +442,49 @@ size_t batch_ws_bytes(const hh_params *p, int32_t n, bool with_holo) {
   return total;
 }
 
-// Validates every item, then enqueues: per stack the Fresnel transform (frames
-// given) and the covariance; one launch for all eigenproblems; per stack the
-// projection and image.
+// Second stream of each device for the batch schedule below (created once, default
+// priority, not synchronising with the null stream).
+std::mutex g_side_mu;
+hipStream_t g_side[64] = {};
+
+hipError_t side_stream(hipStream_t *out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> g(g_side_mu);
+  if (!g_side[dev]) {
+    e = hipStreamCreateWithFlags(&g_side[dev], hipStreamNonBlocking);
+    if (e != hipSuccess) return e;
+  }
+  *out = g_side[dev];
+  return hipSuccess;
+}
+
+// Stacks whose eigenproblems go first: those of the largest solver class present
+// (n > 32, then n > 16); when every stack is in that class, the first half.  Empty
+// when the batch has one stack.
+std::vector<int> early_stacks(const hh_params *p, int n) {
+  std::vector<int> first;
+  if (n < 2) return first;
+  int top = 0;
+  for (int i = 0; i < n; ++i) top = std::max(top, p[i].nt > 32 ? 2 : p[i].nt > 16 ? 1 : 0);
+  for (int i = 0; i < n; ++i)
+    if ((p[i].nt > 32 ? 2 : p[i].nt > 16 ? 1 : 0) == top) first.push_back(i);
+  if ((int)first.size() == n) first.resize((n + 1) / 2);
+  return first;
+}
+
+// Validates every item, then enqueues.  Schedule: the transforms and covariances of
+// the early stacks (early_stacks) on s; then, on a second stream that waits for them,
+// their eigenproblems (one launch per solver class) and projections, while s goes on
+// with the transforms, covariances, eigenproblems and projections of the other
+// stacks; s finally waits for the second stream.  The eigensolver is one workgroup
+// per problem and latency-bound, so its run on the second stream overlaps the
+// bandwidth-bound work of other stacks.  `side` is that second stream (nullptr: the
+// device's own).  Each stack's results do not depend on the schedule.
 hh_status run_batch(const hh_params *p, int n, const BatchItem *it, void *workspace, size_t ws_bytes, hipStream_t s,
-                    const char *who) {
+                    const char *who, hipStream_t side = nullptr) {
   const bool with_holo = it[0].frames != nullptr;
   size_t need = 0;
   for (int i = 0; i < n; ++i) {
@@ -471,11 +509,19 @@ hh_status run_batch(const hh_params *p, int n, const BatchItem *it, void *worksp
       if (!(plans[i] = get_plan(p[i]))) return HH_E_DEVICE;
   std::vector<EighProblem> probs(n);
   std::vector<StackViews> views(n);
-  char *ws = static_cast<char *>(workspace);
-  hipError_t e = hipSuccess;
-  for (int i = 0; i < n && e == hipSuccess; ++i) {
+  std::vector<size_t> offs(n);
+  {
+    size_t o = 0;
+    for (int i = 0; i < n; ++i) {
+      offs[i] = o;
+      o += align_up(pipe_layout(p + i, with_holo).total);
+    }
+  }
+  char *ws0 = static_cast<char *>(workspace);
+  auto front = [&](int i) {
     const PipeLayout L = pipe_layout(p + i, with_holo);
-    e = enqueue_front(p[i], plans[i], L, ws, it[i].frames, it[i].holo, views[i], s);
+    char *ws = ws0 + offs[i];
+    const hipError_t e = enqueue_front(p[i], plans[i], L, ws, it[i].frames, it[i].holo, views[i], s);
     probs[i] = EighProblem{p[i].nt,
                            views[i].cov,
                            it[i].evals ? it[i].evals : reinterpret_cast<double *>(ws + L.evals),
@@ -485,10 +531,55 @@ hh_status run_batch(const hh_params *p, int n, const BatchItem *it, void *worksp
                            views[i].g2,
                            views[i].D,
                            p[i].eigh_solver};
-    ws += align_up(L.total);
+    return e;
+  };
+  auto back = [&](const std::vector<int> &set, hipStream_t st) {
+    std::vector<EighProblem> sub;
+    for (int i : set) sub.push_back(probs[i]);
+    hipError_t e = sub.empty() ? hipSuccess : launch_eigh_batch(sub.data(), (int)sub.size(), 40, st);
+    for (size_t k = 0; k < set.size() && e == hipSuccess; ++k)
+      e = enqueue_back(p[set[k]], views[set[k]], probs[set[k]].evecs, it[set[k]].image, st);
+    return e;
+  };
+  const std::vector<int> early = early_stacks(p, n);
+  std::vector<char> is_early(n, 0);
+  for (int i : early) is_early[i] = 1;
+  std::vector<int> late;
+  for (int i = 0; i < n; ++i)
+    if (!is_early[i]) late.push_back(i);
+
+  hipError_t e = hipSuccess;
+  if (early.empty()) {
+    for (int i = 0; i < n && e == hipSuccess; ++i) e = front(i);
+    if (e == hipSuccess) e = back(late, s);
+    if (e != hipSuccess) return device_fail(e, who);
+    return HH_OK;
   }
-  if (e == hipSuccess) e = launch_eigh_batch(probs.data(), n, 40, s);
-  for (int i = 0; i < n && e == hipSuccess; ++i) e = enqueue_back(p[i], views[i], probs[i].evecs, it[i].image, s);
+  if (!side && (e = side_stream(&side)) != hipSuccess) return device_fail(e, who);
+  hipEvent_t fork = nullptr, join = nullptr;
+  if ((e = hipEventCreateWithFlags(&fork, hipEventDisableTiming)) != hipSuccess) return device_fail(e, who);
+  if ((e = hipEventCreateWithFlags(&join, hipEventDisableTiming)) != hipSuccess) {
+    (void)hipEventDestroy(fork);
+    return device_fail(e, who);
+  }
+  for (size_t k = 0; k < early.size() && e == hipSuccess; ++k) e = front(early[k]);
+  bool forked = false;
+  if (e == hipSuccess) e = hipEventRecord(fork, s);
+  if (e == hipSuccess) e = hipStreamWaitEvent(side, fork, 0);
+  if (e == hipSuccess) {
+    forked = true;
+    e = back(early, side);
+  }
+  for (size_t k = 0; k < late.size() && e == hipSuccess; ++k) e = front(late[k]);
+  if (e == hipSuccess) e = back(late, s);
+  // the join is enqueued whenever the fork was, so that a capture stays joined
+  if (forked) {
+    hipError_t ej = hipEventRecord(join, side);
+    if (ej == hipSuccess) ej = hipStreamWaitEvent(s, join, 0);
+    if (e == hipSuccess) e = ej;
+  }
+  (void)hipEventDestroy(fork);
+  (void)hipEventDestroy(join);
   if (e != hipSuccess) return device_fail(e, who);
   return HH_OK;
 }
@@ -827,18 +918,26 @@ hh_status hh_graph_create(const hh_params *p, int32_t n, const hh_stack *stacks,
     }
     if (!get_plan(p[i])) return HH_E_DEVICE;  // tables allocated here, outside the capture
   }
-  hipStream_t cs = nullptr;
+  // the capture stream and the second stream of the batch schedule (its branch of the graph)
+  hipStream_t cs = nullptr, cs2 = nullptr;
   hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
   if (e != hipSuccess) return device_fail(e, "hh_graph_create (stream)");
+  e = hipStreamCreateWithFlags(&cs2, hipStreamNonBlocking);
+  if (e != hipSuccess) {
+    (void)hipStreamDestroy(cs);
+    return device_fail(e, "hh_graph_create (stream)");
+  }
   e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
   if (e != hipSuccess) {
     (void)hipStreamDestroy(cs);
+    (void)hipStreamDestroy(cs2);
     return device_fail(e, "hh_graph_create (begin capture)");
   }
-  const hh_status st = run_batch(p, n, items.data(), workspace, ws_bytes, cs, "hh_graph_create");
+  const hh_status st = run_batch(p, n, items.data(), workspace, ws_bytes, cs, "hh_graph_create", cs2);
   hipGraph_t graph = nullptr;
   const hipError_t e2 = hipStreamEndCapture(cs, &graph);
   (void)hipStreamDestroy(cs);
+  (void)hipStreamDestroy(cs2);
   if (st != HH_OK) {
     if (graph) (void)hipGraphDestroy(graph);
     return st;
