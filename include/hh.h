@@ -337,7 +337,12 @@ hh_status hh_analyze_batch(const hh_params *p, int32_t n, const hh_window *wins,
 /*
  * The work of one hh_pipeline_batch call, captured once as a HIP graph and
  * replayed with one launch (steps (a)-(e) on n uneven stacks; no allocation or
- * host work per replay).  The pointers in p/stacks/workspace are baked into the
+ * host work per replay).  Its schedule differs from the eager call's and not its
+ * results: the stacks of the largest eigenproblem class present (n_t > 32, else
+ * > 16; the first half when all are in one class) are transformed first, and their
+ * eigenproblems and projections run on a second graph branch beside the transforms,
+ * eigenproblems and projections of the other stacks, so the single-workgroup solves
+ * overlap bandwidth-bound work.  The pointers in p/stacks/workspace are baked into the
  * graph: every replay reads the CURRENT contents of the same frame buffers and
  * rewrites the same outputs, so a caller refills the frames between replays.
  * The buffers must outlive the graph; replays on one workspace must not overlap.

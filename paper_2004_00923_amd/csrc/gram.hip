@@ -1,7 +1,10 @@
 // Step (b), Eq. (4): C = H^{t*} H as a tall-skinny split-K Gram on FP32 MFMA.
 //
-// With R = A + iB (A, B real, one column per frame):
-//   Re R^H R = A^T A + B^T B,   Im (R^H R)[s][t] = (A^T B)[s][t] - (A^T B)[t][s].
+// With R = A + iB (A, B real, one column per frame) and M = A^T B:
+//   Re R^H R = A^T A + B^T B = (A + B)^T (A + B) - M - M^T,
+//   Im (R^H R)[s][t] = M[s][t] - M[t][s],
+// so the FP32 forms take three real products per block pair (N = (A + B)^T (A + B)
+// on the upper blocks, M on all of them) and form Re in FP64 from the summed N, M.
 // Each wave streams its own pixel range straight from HBM in MFMA operand layout
 // (lanes = frames, MFMA k-slots = pixels); there is no LDS or barrier in the
 // main loop.
@@ -52,6 +55,21 @@ __device__ __forceinline__ float sum16(float v) {
 __device__ __forceinline__ float sum32(float v) {
   v = sum16(v);
   return v + __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(v), 0x401F));
+}
+
+// The real part of R^H R from N = (A + B)^T (A + B) and M = A^T B (R = A + iB):
+//   A^T A + B^T B = N - M - M^T,
+// three real products per block pair instead of four.  red holds N's upper blocks
+// in [0, D*D) and M in [D*D, 2*D*D), summed in FP64; the upper triangle of the
+// first area becomes S = Re R^H R (the part the assembly reads).  Each thread
+// rewrites entries it alone reads and writes, then the block synchronises.
+template <int D>
+__device__ __forceinline__ void n_to_s(double *red, int tid) {
+  for (int e = tid; e < D * D; e += 256) {
+    const int i = e / D, j = e % D;
+    if (i <= j) red[e] = red[e] - red[D * D + i * D + j] - red[D * D + j * D + i];
+  }
+  __syncthreads();
 }
 
 // n_t <= 32 path on v_mfma_f32_16x16x4f32: lane (f, k), f = lane % 16, k = lane / 16,
@@ -147,16 +165,16 @@ __global__ __launch_bounds__(256) void gram_partial16(const float2 *__restrict__
         }
         a0r += mr * x0.x + mi * x0.y;
         a0i += mr * x0.y - mi * x0.x;
-        S00 = __builtin_amdgcn_mfma_f32_16x16x4f32(x0.x, x0.x, S00, 0, 0, 0);
-        S00 = __builtin_amdgcn_mfma_f32_16x16x4f32(x0.y, x0.y, S00, 0, 0, 0);
+        // S holds N = (A + B)^T (A + B): one product per block instead of two
+        const float u0 = x0.x + x0.y;
+        S00 = __builtin_amdgcn_mfma_f32_16x16x4f32(u0, u0, S00, 0, 0, 0);
         Q00 = __builtin_amdgcn_mfma_f32_16x16x4f32(x0.x, x0.y, Q00, 0, 0, 0);
         if constexpr (TWO) {
           a1r += mr * x1.x + mi * x1.y;
           a1i += mr * x1.y - mi * x1.x;
-          S01 = __builtin_amdgcn_mfma_f32_16x16x4f32(x0.x, x1.x, S01, 0, 0, 0);
-          S01 = __builtin_amdgcn_mfma_f32_16x16x4f32(x0.y, x1.y, S01, 0, 0, 0);
-          S11 = __builtin_amdgcn_mfma_f32_16x16x4f32(x1.x, x1.x, S11, 0, 0, 0);
-          S11 = __builtin_amdgcn_mfma_f32_16x16x4f32(x1.y, x1.y, S11, 0, 0, 0);
+          const float u1 = x1.x + x1.y;
+          S01 = __builtin_amdgcn_mfma_f32_16x16x4f32(u0, u1, S01, 0, 0, 0);
+          S11 = __builtin_amdgcn_mfma_f32_16x16x4f32(u1, u1, S11, 0, 0, 0);
           Q01 = __builtin_amdgcn_mfma_f32_16x16x4f32(x0.x, x1.y, Q01, 0, 0, 0);
           Q10 = __builtin_amdgcn_mfma_f32_16x16x4f32(x1.x, x0.y, Q10, 0, 0, 0);
           Q11 = __builtin_amdgcn_mfma_f32_16x16x4f32(x1.x, x1.y, Q11, 0, 0, 0);
@@ -197,6 +215,7 @@ __global__ __launch_bounds__(256) void gram_partial16(const float2 *__restrict__
     }
     __syncthreads();
   }
+  n_to_s<D>(red, tid);
   double *out = partial + (size_t)blockIdx.x * partial_len(D);
   for (int i = tid; i < 2 * D * D; i += 256) out[i] = red[i];
   if (tid < D) {
@@ -220,7 +239,7 @@ __global__ __launch_bounds__(256) void gram_partial16(const float2 *__restrict__
 
 // 32 < n_t <= 64 path on v_mfma_f32_32x32x2f32: lane (fr, half) holds frames fr and
 // 32 + fr; the two half-waves take one half of the wave's pixels each.
-__global__ __launch_bounds__(256) void gram_partial64(const float2 *__restrict__ H, int nt, long long npix,
+__global__ __launch_bounds__(256, 2) void gram_partial64(const float2 *__restrict__ H, int nt, long long npix,
                                                       int pxw, double *__restrict__ partial) {
   constexpr int D = 64;
   const int HALF = pxw / 2;  // pixels per half-wave
@@ -252,25 +271,37 @@ __global__ __launch_bounds__(256) void gram_partial64(const float2 *__restrict__
   for (int b = 0; b < 2; ++b) {
     const int t = 32 * b + fr;
     valid[b] = t < nt;
-    src[b] = reinterpret_cast<const float4 *>(H + (long long)(valid[b] ? t : 0) * npix + p0);
+    src[b] = reinterpret_cast<const float4 *>(H + (long long)(valid[b] ? t : 0) * npix);
   }
-
-  for (int s0 = 0; s0 < HALF; s0 += 2 * G4) {
-    float4 h[2][G4];
-#pragma unroll
-    for (int b = 0; b < 2; ++b)
-#pragma unroll
-      for (int g = 0; g < G4; ++g) {
-        const long long px = p0 + s0 + 2 * g;
-        h[b][g] = (valid[b] && px < npix) ? src[b][s0 / 2 + g] : make_float4(0.f, 0.f, 0.f, 0.f);
-      }
+  // Loads are unconditional (past the end they read the frame's first pixels; the
+  // prefetch after the last chunk reads that chunk again) and masked when the chunk
+  // is taken up, so the next chunk's loads stay in flight while the current one is
+  // summed.  Chunk: 8 pixels of each of the lane's two frames, 16 floats each.
+  v16f h0, h1, n0, n1;
+  unsigned hmask = 0, nmask = 0;  // bit g: pixel pair g of the chunk is inside the frame
+  auto load = [&](int s, v16f &c0, v16f &c1, unsigned &mask) {
+    mask = 0;
 #pragma unroll
     for (int g = 0; g < G4; ++g) {
+      const long long px = p0 + s + 2 * g;
+      const bool in = px < npix;
+      mask |= in ? (1u << g) : 0u;
+      const float4 x = src[0][in ? (px >> 1) : 0], y = src[1][in ? (px >> 1) : 0];
+      c0[4 * g] = x.x; c0[4 * g + 1] = x.y; c0[4 * g + 2] = x.z; c0[4 * g + 3] = x.w;
+      c1[4 * g] = y.x; c1[4 * g + 1] = y.y; c1[4 * g + 2] = y.z; c1[4 * g + 3] = y.w;
+    }
+  };
+  load(0, h0, h1, hmask);
+  for (int s0 = 0; s0 < HALF; s0 += 2 * G4) {
+    load(s0 + 2 * G4 < HALF ? s0 + 2 * G4 : s0, n0, n1, nmask);
+#pragma unroll
+    for (int g = 0; g < G4; ++g) {
+      const bool in = (hmask >> g) & 1u;
 #pragma unroll
       for (int e = 0; e < 2; ++e) {
         float2 x[2];
-#pragma unroll
-        for (int b = 0; b < 2; ++b) x[b] = e ? make_float2(h[b][g].z, h[b][g].w) : make_float2(h[b][g].x, h[b][g].y);
+        x[0] = (in && valid[0]) ? make_float2(h0[4 * g + 2 * e], h0[4 * g + 2 * e + 1]) : make_float2(0.f, 0.f);
+        x[1] = (in && valid[1]) ? make_float2(h1[4 * g + 2 * e], h1[4 * g + 2 * e + 1]) : make_float2(0.f, 0.f);
         const float mr = sum32(x[0].x + x[1].x) * inv_nt, mi = sum32(x[0].y + x[1].y) * inv_nt;
         const double dmr = mr, dmi = mi;
         mm_acc += dmr * dmr + dmi * dmi;
@@ -284,18 +315,20 @@ __global__ __launch_bounds__(256) void gram_partial64(const float2 *__restrict__
           a_acc[b].x += dmr * rr + dmi * ri;
           a_acc[b].y += dmr * ri - dmi * rr;
         }
-        S[0] = __builtin_amdgcn_mfma_f32_32x32x2f32(x[0].x, x[0].x, S[0], 0, 0, 0);
-        S[0] = __builtin_amdgcn_mfma_f32_32x32x2f32(x[0].y, x[0].y, S[0], 0, 0, 0);
-        S[1] = __builtin_amdgcn_mfma_f32_32x32x2f32(x[0].x, x[1].x, S[1], 0, 0, 0);
-        S[1] = __builtin_amdgcn_mfma_f32_32x32x2f32(x[0].y, x[1].y, S[1], 0, 0, 0);
-        S[2] = __builtin_amdgcn_mfma_f32_32x32x2f32(x[1].x, x[1].x, S[2], 0, 0, 0);
-        S[2] = __builtin_amdgcn_mfma_f32_32x32x2f32(x[1].y, x[1].y, S[2], 0, 0, 0);
+        // S holds N = (A + B)^T (A + B): one product per block instead of two
+        const float u0 = x[0].x + x[0].y, u1 = x[1].x + x[1].y;
+        S[0] = __builtin_amdgcn_mfma_f32_32x32x2f32(u0, u0, S[0], 0, 0, 0);
+        S[1] = __builtin_amdgcn_mfma_f32_32x32x2f32(u0, u1, S[1], 0, 0, 0);
+        S[2] = __builtin_amdgcn_mfma_f32_32x32x2f32(u1, u1, S[2], 0, 0, 0);
         Q[0] = __builtin_amdgcn_mfma_f32_32x32x2f32(x[0].x, x[0].y, Q[0], 0, 0, 0);
         Q[1] = __builtin_amdgcn_mfma_f32_32x32x2f32(x[0].x, x[1].y, Q[1], 0, 0, 0);
         Q[2] = __builtin_amdgcn_mfma_f32_32x32x2f32(x[1].x, x[0].y, Q[2], 0, 0, 0);
         Q[3] = __builtin_amdgcn_mfma_f32_32x32x2f32(x[1].x, x[1].y, Q[3], 0, 0, 0);
       }
     }
+    h0 = n0;
+    h1 = n1;
+    hmask = nmask;
   }
 
   for (int i = tid; i < 2 * D * D; i += 256) red[i] = 0.0;
@@ -321,6 +354,7 @@ __global__ __launch_bounds__(256) void gram_partial64(const float2 *__restrict__
     }
     __syncthreads();
   }
+  n_to_s<D>(red, tid);
   double *out = partial + (size_t)blockIdx.x * partial_len(D);
   for (int i = tid; i < 2 * D * D; i += 256) out[i] = red[i];
   if (tid < D) {

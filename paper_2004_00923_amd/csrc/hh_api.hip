@@ -442,31 +442,11 @@ size_t batch_ws_bytes(const hh_params *p, int32_t n, bool with_holo) {
   return total;
 }
 
-// Second stream of each device for the batch schedule below (created once, default
-// priority, not synchronising with the null stream).
-std::mutex g_side_mu;
-hipStream_t g_side[64] = {};
-
-hipError_t side_stream(hipStream_t *out) {
-  int dev = 0;
-  hipError_t e = hipGetDevice(&dev);
-  if (e != hipSuccess) return e;
-  if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
-  std::lock_guard<std::mutex> g(g_side_mu);
-  if (!g_side[dev]) {
-    e = hipStreamCreateWithFlags(&g_side[dev], hipStreamNonBlocking);
-    if (e != hipSuccess) return e;
-  }
-  *out = g_side[dev];
-  return hipSuccess;
-}
-
-// Stacks whose eigenproblems go first: those of the largest solver class present
-// (n > 32, then n > 16); when every stack is in that class, the first half.  Empty
-// when the batch has one stack.
+// Stacks whose eigenproblems go first in the captured form: those of the largest
+// solver class present (n > 32, then n > 16); when every stack is in that class,
+// the first half.
 std::vector<int> early_stacks(const hh_params *p, int n) {
   std::vector<int> first;
-  if (n < 2) return first;
   int top = 0;
   for (int i = 0; i < n; ++i) top = std::max(top, p[i].nt > 32 ? 2 : p[i].nt > 16 ? 1 : 0);
   for (int i = 0; i < n; ++i)
@@ -475,16 +455,21 @@ std::vector<int> early_stacks(const hh_params *p, int n) {
   return first;
 }
 
-// Validates every item, then enqueues.  Schedule: the transforms and covariances of
-// the early stacks (early_stacks) on s; then, on a second stream that waits for them,
-// their eigenproblems (one launch per solver class) and projections, while s goes on
-// with the transforms, covariances, eigenproblems and projections of the other
-// stacks; s finally waits for the second stream.  The eigensolver is one workgroup
-// per problem and latency-bound, so its run on the second stream overlaps the
-// bandwidth-bound work of other stacks.  `side` is that second stream (nullptr: the
-// device's own).  Each stack's results do not depend on the schedule.
+// Validates every item, then enqueues.
+// Without a branch (eager calls: a caller overlaps batches on streams of its own):
+// on s, every stack's transform and covariance, one eigensolver launch per solver
+// class, then every projection.
+// With a branch stream (the captured form): on s, the transforms and covariances of
+// the early stacks (early_stacks); then on the branch, which waits for them, their
+// eigenproblems (one launch per solver class) and projections, while s goes on with
+// the transforms, covariances, eigenproblems and projections of the other stacks;
+// s finally waits for the branch.  The eigensolver is one workgroup per problem and
+// latency-bound, so its run on the branch overlaps the bandwidth-bound work of the
+// other stacks.  (One branch: with more, the graph runtime placed later transforms
+// in the hardware queue behind a branch's long solve.)  Each stack's results do not
+// depend on the schedule.
 hh_status run_batch(const hh_params *p, int n, const BatchItem *it, void *workspace, size_t ws_bytes, hipStream_t s,
-                    const char *who, hipStream_t side = nullptr) {
+                    const char *who, hipStream_t branch = nullptr) {
   const bool with_holo = it[0].frames != nullptr;
   size_t need = 0;
   for (int i = 0; i < n; ++i) {
@@ -541,21 +526,22 @@ hh_status run_batch(const hh_params *p, int n, const BatchItem *it, void *worksp
       e = enqueue_back(p[set[k]], views[set[k]], probs[set[k]].evecs, it[set[k]].image, st);
     return e;
   };
+
+  hipError_t e = hipSuccess;
+  if (!branch || n < 2) {
+    std::vector<int> all(n);
+    for (int i = 0; i < n; ++i) all[i] = i;
+    for (int i = 0; i < n && e == hipSuccess; ++i) e = front(i);
+    if (e == hipSuccess) e = back(all, s);
+    if (e != hipSuccess) return device_fail(e, who);
+    return HH_OK;
+  }
   const std::vector<int> early = early_stacks(p, n);
   std::vector<char> is_early(n, 0);
   for (int i : early) is_early[i] = 1;
   std::vector<int> late;
   for (int i = 0; i < n; ++i)
     if (!is_early[i]) late.push_back(i);
-
-  hipError_t e = hipSuccess;
-  if (early.empty()) {
-    for (int i = 0; i < n && e == hipSuccess; ++i) e = front(i);
-    if (e == hipSuccess) e = back(late, s);
-    if (e != hipSuccess) return device_fail(e, who);
-    return HH_OK;
-  }
-  if (!side && (e = side_stream(&side)) != hipSuccess) return device_fail(e, who);
   hipEvent_t fork = nullptr, join = nullptr;
   if ((e = hipEventCreateWithFlags(&fork, hipEventDisableTiming)) != hipSuccess) return device_fail(e, who);
   if ((e = hipEventCreateWithFlags(&join, hipEventDisableTiming)) != hipSuccess) {
@@ -565,16 +551,16 @@ hh_status run_batch(const hh_params *p, int n, const BatchItem *it, void *worksp
   for (size_t k = 0; k < early.size() && e == hipSuccess; ++k) e = front(early[k]);
   bool forked = false;
   if (e == hipSuccess) e = hipEventRecord(fork, s);
-  if (e == hipSuccess) e = hipStreamWaitEvent(side, fork, 0);
+  if (e == hipSuccess) e = hipStreamWaitEvent(branch, fork, 0);
   if (e == hipSuccess) {
     forked = true;
-    e = back(early, side);
+    e = back(early, branch);
   }
   for (size_t k = 0; k < late.size() && e == hipSuccess; ++k) e = front(late[k]);
   if (e == hipSuccess) e = back(late, s);
-  // the join is enqueued whenever the fork was, so that a capture stays joined
+  // the join is enqueued whenever the fork was, so that a capture ends joined
   if (forked) {
-    hipError_t ej = hipEventRecord(join, side);
+    hipError_t ej = hipEventRecord(join, branch);
     if (ej == hipSuccess) ej = hipStreamWaitEvent(s, join, 0);
     if (e == hipSuccess) e = ej;
   }
@@ -918,26 +904,27 @@ hh_status hh_graph_create(const hh_params *p, int32_t n, const hh_stack *stacks,
     }
     if (!get_plan(p[i])) return HH_E_DEVICE;  // tables allocated here, outside the capture
   }
-  // the capture stream and the second stream of the batch schedule (its branch of the graph)
-  hipStream_t cs = nullptr, cs2 = nullptr;
+  // the capture stream and the stream of the graph's second branch
+  hipStream_t cs = nullptr, br = nullptr;
   hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
-  if (e != hipSuccess) return device_fail(e, "hh_graph_create (stream)");
-  e = hipStreamCreateWithFlags(&cs2, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&br, hipStreamNonBlocking);
+  auto destroy_streams = [&]() {
+    if (cs) (void)hipStreamDestroy(cs);
+    if (br) (void)hipStreamDestroy(br);
+  };
   if (e != hipSuccess) {
-    (void)hipStreamDestroy(cs);
+    destroy_streams();
     return device_fail(e, "hh_graph_create (stream)");
   }
   e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
   if (e != hipSuccess) {
-    (void)hipStreamDestroy(cs);
-    (void)hipStreamDestroy(cs2);
+    destroy_streams();
     return device_fail(e, "hh_graph_create (begin capture)");
   }
-  const hh_status st = run_batch(p, n, items.data(), workspace, ws_bytes, cs, "hh_graph_create", cs2);
+  const hh_status st = run_batch(p, n, items.data(), workspace, ws_bytes, cs, "hh_graph_create", br);
   hipGraph_t graph = nullptr;
   const hipError_t e2 = hipStreamEndCapture(cs, &graph);
-  (void)hipStreamDestroy(cs);
-  (void)hipStreamDestroy(cs2);
+  destroy_streams();
   if (st != HH_OK) {
     if (graph) (void)hipGraphDestroy(graph);
     return st;
