@@ -11,11 +11,14 @@
 // theta = g / (2|beta|), rewritten to need two square roots and one division).
 //
 // Work split per round: (1) every thread rotates the 2x2 blocks {p1,q1} x {p2,q2}
-// of A it owns, in place (the four outputs share the four inputs); barrier;
+// of A it owns, in place (the four outputs share the four inputs; only the upper
+// triangle of A is kept, so each entry is read and written once); barrier;
 // (2) wave 0 computes the next round's rotations from three entries each, with
 // hardware reciprocal / reciprocal-square-root seeds refined by Newton steps,
-// while the other waves rotate V's (row, pair) entries in place; barrier.  C is scaled
-// by an exact power of two so that its Frobenius norm is O(1).
+// while the other waves rotate V's (row, pair) entries in place, one row per lane
+// and one pair per group of lanes (the group's rotation data is one LDS
+// broadcast); barrier.  C is scaled by an exact power of two so that its Frobenius
+// norm is O(1).
 // A rotation is skipped when |beta| <= 1e-15 sqrt(|a b|) or |beta| <= 1e-18 ||C||_F;
 // the iteration stops when every off-diagonal entry passes that test.  The result
 // is sorted by decreasing eigenvalue and each eigenvector's phase is fixed.
@@ -57,14 +60,14 @@ __device__ __forceinline__ double rcp64(double x) {
   return y;
 }
 
-// Per-round rotation data, indexed by matrix index i: whether i's pair rotates, c_i,
-// e_i = J[partner][i] and the new diagonal (the pairs are recomputed by pair_of).
+// Per-round rotation data, indexed by matrix index i: cd[i] = (c_i, new diagonal
+// entry i), e[i] = J[partner][i].  A pair rotates iff its e is nonzero (a rotating
+// pair has |beta| > 1e-18 ||C||_F after scaling, so e cannot underflow to zero);
+// a pair that does not rotate has c = 1, e = 0 and its diagonal entries as they are.
 template <int NMAX>
 struct RoundParams {
-  int rot[NMAX];
-  double c[NMAX];
+  double2 cd[NMAX];
   double2 e[NMAX];
-  double d[NMAX];
 };
 
 // Round-robin pairing: pair k of round r among m players (p < q; q may be the dummy).
@@ -84,16 +87,15 @@ __device__ __forceinline__ void pair_of(int r, int k, int m, int &p, int &q) {
 }
 
 template <int NMAX>
-__device__ __forceinline__ void set_rotation(RoundParams<NMAX> &P, int k, int p, int q, int n, double a, double b,
+__device__ __forceinline__ void set_rotation(RoundParams<NMAX> &P, int p, int q, int n, double a, double b,
                                              double2 beta, double abs2) {
   if (q >= n) {  // paired with the dummy index: no rotation
-    P.rot[p] = 0;
-    P.c[p] = 1.0;
+    P.cd[p] = make_double2(1.0, a);
     P.e[p] = make_double2(0.0, 0.0);
     return;
   }
   // computed whether or not the pair rotates, then selected (no branch around the
-  // arithmetic; a pair that does not rotate gets c = 1, e = 0 and its diagonal as is)
+  // arithmetic)
   const double ab2 = beta.x * beta.x + beta.y * beta.y;
   const bool rot = ab2 > kRelTol * kRelTol * fabs(a * b) && ab2 > abs2;
   const double g = b - a, ag = fabs(g), sg = g >= 0.0 ? 1.0 : -1.0;
@@ -104,14 +106,23 @@ __device__ __forceinline__ void set_rotation(RoundParams<NMAX> &P, int k, int p,
   const double c = rot ? (D + ag) * inv : 1.0;
   const double2 eq = rot ? make_double2(sg * 2.0 * inv * beta.x, sg * 2.0 * inv * beta.y)  // J[p][q]
                          : make_double2(0.0, 0.0);
-  P.c[p] = c;
-  P.c[q] = c;
+  P.cd[p] = make_double2(c, rot ? a - tab : a);
+  P.cd[q] = make_double2(c, rot ? b + tab : b);
   P.e[q] = eq;
   P.e[p] = rot ? make_double2(-eq.x, eq.y) : make_double2(0.0, 0.0);  // J[q][p] = -conj(J[p][q])
-  P.d[p] = rot ? a - tab : a;
-  P.d[q] = rot ? b + tab : b;
-  P.rot[p] = rot ? 1 : 0;
-  P.rot[q] = rot ? 1 : 0;
+}
+
+// Entry (i, j) of the Hermitian A, of which only the upper triangle (i <= j) is
+// kept up to date.
+__device__ __forceinline__ double2 herm(const double2 *A, int LD, int i, int j) {
+  const bool up = i <= j;
+  const double2 v = A[(up ? i : j) * LD + (up ? j : i)];
+  return make_double2(v.x, up ? v.y : -v.y);
+}
+// Writes entry (i, j) at its upper-triangle position.
+__device__ __forceinline__ void herm_store(double2 *A, int LD, int i, int j, double2 v) {
+  const bool up = i <= j;
+  A[(up ? i : j) * LD + (up ? j : i)] = make_double2(v.x, up ? v.y : -v.y);
 }
 
 // C into A (scaled by an exact power of two so that its Frobenius norm is O(1))
@@ -246,8 +257,6 @@ __global__ __launch_bounds__(threads_for<NMAX>()) void eigh_jacobi(EighBatch bat
   constexpr int NPMAX = NMAX / 2;
   constexpr int NBLK = NPMAX * (NPMAX + 1) / 2;
   constexpr int BPT = (NBLK + kThreads - 1) / kThreads;          // A blocks per thread
-  constexpr int VTH = kThreads - 64;                              // threads rotating V (waves 1..)
-  constexpr int VPT = (NMAX * NPMAX + VTH - 1) / VTH;             // V (row, pair) items per thread
   extern __shared__ double2 smem[];
   double2 *const A = smem;              // [n][LD]
   double2 *const V = smem + NMAX * LD;  // [n][LD]
@@ -277,15 +286,14 @@ __global__ __launch_bounds__(threads_for<NMAX>()) void eigh_jacobi(EighBatch bat
     }
   }
 
-  // V items (row, pair) of this thread (waves 1..), fixed for every round
-  int vRow[VPT], vK[VPT];
-#pragma unroll
-  for (int u = 0; u < VPT; ++u) {
-    const int it = (tid - 64) + VTH * u;
-    const bool ok = tid >= 64 && it < n * np;
-    vRow[u] = ok ? it / np : -1;
-    vK[u] = ok ? it - (it / np) * np : 0;
-  }
+  // V items: waves 1.. rotate V with one row per lane, the wave's lanes in groups of
+  // NMAX rows that each take one pair, so the rotation data a group reads is one
+  // LDS broadcast.  Item g of a wave is the pairs GPW g .. GPW g + GPW - 1.
+  constexpr int GPW = 64 / NMAX;                  // pairs per wave and item
+  constexpr int VW = kThreads / 64 - 1;           // waves rotating V
+  constexpr int NG = NPMAX / GPW;                 // items
+  constexpr int VPT = (NG + VW - 1) / VW;         // items per wave
+  const int vrow = (tid & 63) % NMAX, vsub = (tid & 63) / NMAX, vwave = (tid >> 6) - 1;
 
   const double scale = load_scaled<NMAX, kThreads>(pr, A, V, red);
   const double fro = red[0] / scale;  // Frobenius norm of C (exactly, scale is a power of two)
@@ -317,14 +325,15 @@ __global__ __launch_bounds__(threads_for<NMAX>()) void eigh_jacobi(EighBatch bat
       int p, q;
       pair_of(0, tid, m, p, q);
       const int qc = q < n ? q : p;
-      set_rotation(prm[0], tid, p, q, n, A[p * LD + p].x, A[qc * LD + qc].x, A[p * LD + qc], abs2);
+      set_rotation(prm[0], p, q, n, A[p * LD + p].x, A[qc * LD + qc].x, A[p * LD + qc], abs2);
     }
     __syncthreads();
 
     int pb = 0;
     for (int r = 0; r < m - 1; ++r) {
       const RoundParams<NMAX> &P = prm[pb];
-      // (1) A <- J^H A J on the blocks this thread owns (in place: a block has one owner)
+      // (1) A <- J^H A J on the blocks this thread owns (in place: an entry of the upper
+      // triangle belongs to one block)
 #pragma unroll
       for (int u = 0; u < BPT; ++u) {
         if (bP[u] < 0) continue;
@@ -333,23 +342,24 @@ __global__ __launch_bounds__(threads_for<NMAX>()) void eigh_jacobi(EighBatch bat
         pair_of(r, bP[u], m, p1, q1);
         pair_of(r, bQ[u], m, p2, q2);
         // One instruction stream for the pair's own block (P == Q) and the others:
-        // every operand is loaded first; on the own block the rotated values are
-        // replaced by the exact ones (zero off-diagonal, moved diagonal) or, when the
-        // pair does not rotate, by the entries as they were.
+        // every operand is loaded first; on the own block of a rotating pair the
+        // rotated values are replaced by the exact ones (zero off-diagonal, moved
+        // diagonal).  A pair that does not rotate has c = 1, e = 0, for which the
+        // products below return its entries unchanged.
         const bool own = bP[u] == bQ[u];
         const bool vq1 = q1 < n, vq2 = q2 < n;
         // value selects (clamped indices), never a select between LDS and a local
         const int q1c = vq1 ? q1 : p1, q2c = vq2 ? q2 : p2;
         const double m1 = vq1 ? 1.0 : 0.0, m2 = vq2 ? 1.0 : 0.0;
-        const double2 a = A[p1 * LD + p2];
-        const double2 b = zscale(A[p1 * LD + q2c], m2);
-        const double2 d = zscale(A[q1c * LD + p2], m1);
-        const double2 f = zscale(A[q1c * LD + q2c], m1 * m2);
-        const double c1 = P.c[p1], c2 = P.c[p2];
+        const double2 a = herm(A, LD, p1, p2);
+        const double2 b = zscale(herm(A, LD, p1, q2c), m2);
+        const double2 d = zscale(herm(A, LD, q1c, p2), m1);
+        const double2 f = zscale(herm(A, LD, q1c, q2c), m1 * m2);
+        const double2 cd1 = P.cd[p1];
+        const double c1 = cd1.x, dp = cd1.y, dq = P.cd[q1c].y, c2 = P.cd[p2].x;
         const double2 e1 = zscale(P.e[q1c], m1);  // J[p1][q1]
         const double2 e2 = zscale(P.e[q2c], m2);  // J[p2][q2]
-        const bool rot = P.rot[p1] != 0;
-        const double dp = P.d[p1], dq = P.d[q1c];
+        const bool rot = e1.x != 0.0 || e1.y != 0.0;
         // T = M J2 (columns p2, q2), then J1^H T (rows p1, q1)
         const double2 me2c = make_double2(-e2.x, e2.y);  // J[q2][p2]
         const double2 t00 = zadd(zscale(a, c2), zmul(b, me2c)), t01 = zadd(zmul(a, e2), zscale(b, c2));
@@ -357,30 +367,17 @@ __global__ __launch_bounds__(threads_for<NMAX>()) void eigh_jacobi(EighBatch bat
         double2 o00 = zsub(zscale(t00, c1), zmul(e1, t10));
         double2 o01 = zsub(zscale(t01, c1), zmul(e1, t11));
         const double2 e1c = zconj(e1);
-        double2 o10 = zadd(zmul(e1c, t00), zscale(t10, c1));
+        const double2 o10 = zadd(zmul(e1c, t00), zscale(t10, c1));
         double2 o11 = zadd(zmul(e1c, t01), zscale(t11, c1));
-        if (own) {
-          o00 = make_double2(rot ? dp : a.x, 0.0);
-          o11 = make_double2(rot ? dq : f.x, 0.0);
-          o01 = rot ? make_double2(0.0, 0.0) : b;
-          o10 = zconj(o01);
+        if (own && rot) {
+          o00 = make_double2(dp, 0.0);
+          o11 = make_double2(dq, 0.0);
+          o01 = make_double2(0.0, 0.0);
         }
-        // on the own block the mirrored write of a diagonal entry is to the same
-        // address: it goes first, so that the entry keeps a +0 imaginary part
-        A[p2 * LD + p1] = zconj(o00);
-        A[p1 * LD + p2] = o00;
-        if (vq2) {
-          A[q2 * LD + p1] = zconj(o01);
-          A[p1 * LD + q2] = o01;
-        }
-        if (vq1) {
-          A[p2 * LD + q1] = zconj(o10);
-          A[q1 * LD + p2] = o10;
-        }
-        if (vq1 && vq2) {
-          A[q2 * LD + q1] = zconj(o11);
-          A[q1 * LD + q2] = o11;
-        }
+        herm_store(A, LD, p1, p2, o00);
+        if (vq2) herm_store(A, LD, p1, q2, o01);
+        if (vq1 && !own) herm_store(A, LD, q1, p2, o10);  // on the own block: o01's entry
+        if (vq1 && vq2) herm_store(A, LD, q1, q2, o11);
       }
       __syncthreads();
       if (tid < 64) {
@@ -389,40 +386,36 @@ __global__ __launch_bounds__(threads_for<NMAX>()) void eigh_jacobi(EighBatch bat
           int p, q;
           pair_of(r + 1, tid, m, p, q);
           const int qc = q < n ? q : p;
-          set_rotation(prm[pb ^ 1], tid, p, q, n, A[p * LD + p].x, A[qc * LD + qc].x, A[p * LD + qc], abs2);
+          set_rotation(prm[pb ^ 1], p, q, n, A[p * LD + p].x, A[qc * LD + qc].x, A[p * LD + qc], abs2);
         }
       } else {
-        // (2b) waves 1..3: V <- V J on (row, pair) items in place: every operand is
-        // loaded first, then the items are rotated (a pair that does not rotate has
-        // c = 1, e = 0 and is rotated all the same: no dependent branch)
-        constexpr int VC = NMAX <= 32 ? VPT : 2;  // items loaded together (registers)
+        // (2b) waves 1..: V <- V J, one (row, pair) entry pair per lane and item; every
+        // operand is loaded first, then the items are rotated (a pair that does not
+        // rotate has c = 1, e = 0 and is rotated all the same)
+        double2 vp[VPT], vq[VPT], eq[VPT], ep[VPT];
+        double cc[VPT];
+        int ip[VPT], iq[VPT];
 #pragma unroll
-        for (int u0 = 0; u0 < VPT; u0 += VC) {
-          double2 vp[VC], vq[VC], eq[VC], ep[VC];
-          double cc[VC];
-          int ip[VC], iq[VC];
+        for (int u = 0; u < VPT; ++u) {
+          const int k = (vwave + VW * u) * GPW + vsub;
+          const bool ok = vwave + VW * u < NG && k < np && vrow < n;
+          int p = 0, q = 0;
+          if (ok) pair_of(r, k, m, p, q);
+          const int row = ok ? vrow : 0;
+          const int qc = q < n ? q : p;
+          ip[u] = row * LD + p;
+          iq[u] = ok && q < n ? row * LD + q : -1;
+          vp[u] = V[row * LD + p];
+          vq[u] = V[row * LD + qc];
+          cc[u] = P.cd[p].x;
+          eq[u] = P.e[qc];  // J[p][q]
+          ep[u] = P.e[p];   // J[q][p]
+        }
 #pragma unroll
-          for (int w = 0; w < VC; ++w) {
-            const int u = u0 + w < VPT ? u0 + w : VPT - 1;
-            const bool ok = u0 + w < VPT && vRow[u] >= 0;
-            int p = 0, q = 0;
-            if (ok) pair_of(r, vK[u], m, p, q);
-            const int row = ok ? vRow[u] : 0;
-            const int qc = q < n ? q : p;
-            ip[w] = row * LD + p;
-            iq[w] = ok && q < n ? row * LD + q : -1;
-            vp[w] = V[row * LD + p];
-            vq[w] = V[row * LD + qc];
-            cc[w] = P.c[p];
-            eq[w] = P.e[qc];  // J[p][q]
-            ep[w] = P.e[p];   // J[q][p]
-          }
-#pragma unroll
-          for (int w = 0; w < VC; ++w) {
-            if (iq[w] >= 0) {
-              V[ip[w]] = zadd(zscale(vp[w], cc[w]), zmul(vq[w], ep[w]));
-              V[iq[w]] = zadd(zmul(vp[w], eq[w]), zscale(vq[w], cc[w]));
-            }
+        for (int u = 0; u < VPT; ++u) {
+          if (iq[u] >= 0) {
+            V[ip[u]] = zadd(zscale(vp[u], cc[u]), zmul(vq[u], ep[u]));
+            V[iq[u]] = zadd(zmul(vp[u], eq[u]), zscale(vq[u], cc[u]));
           }
         }
       }
