@@ -480,19 +480,35 @@ __global__ __launch_bounds__(256) void gram_partial_lp(const float2 *__restrict_
   const float inv_nt = 1.0f / (float)nt;
   const long long p0 = ((long long)blockIdx.x * 4 + wave) * pxw;
   const bool v0 = f < nt, v1 = (16 + f) < nt;
-  const float4 *s0p = reinterpret_cast<const float4 *>(H + (long long)(v0 ? f : 0) * npix + p0) + kq;
-  const float4 *s1p = reinterpret_cast<const float4 *>(H + (long long)(v1 ? 16 + f : 0) * npix + p0) + kq;
+  const float4 *s0p = reinterpret_cast<const float4 *>(H + (long long)(v0 ? f : 0) * npix);
+  const float4 *s1p = reinterpret_cast<const float4 *>(H + (long long)(v1 ? 16 + f : 0) * npix);
 
-  auto load_step = [&](int j, float2 (&x0)[8], float2 (&x1)[8]) {
+  // One step: pixels 8g + 2kq, 8g + 2kq + 1 (g < 4) of the wave's 32, of frames f and
+  // 16 + f.  Loads are unconditional (past the end they read the frame's first
+  // pixels) and masked when the step is unpacked, so that a prefetched step's loads
+  // stay in flight while the current step is summed; a step is held in vector
+  // registers (16 floats per frame stream).
+  auto load_raw = [&](int j, v16f &c0, v16f &c1, unsigned &mask) {
+    mask = 0;
 #pragma unroll
     for (int g = 0; g < 4; ++g) {
-      const bool in = p0 + 32 * j + 8 * g + 2 * kq < npix;
-      const float4 a = (v0 && in) ? s0p[16 * j + 4 * g] : make_float4(0.f, 0.f, 0.f, 0.f);
-      const float4 b = (v1 && in) ? s1p[16 * j + 4 * g] : make_float4(0.f, 0.f, 0.f, 0.f);
-      x0[2 * g] = make_float2(a.x, a.y);
-      x0[2 * g + 1] = make_float2(a.z, a.w);
-      x1[2 * g] = make_float2(b.x, b.y);
-      x1[2 * g + 1] = make_float2(b.z, b.w);
+      const long long px = p0 + 32 * j + 8 * g + 2 * kq;
+      const bool in = px < npix;
+      mask |= in ? (1u << g) : 0u;
+      const float4 a = s0p[in ? (px >> 1) : 0], b = s1p[in ? (px >> 1) : 0];
+      c0[4 * g] = a.x; c0[4 * g + 1] = a.y; c0[4 * g + 2] = a.z; c0[4 * g + 3] = a.w;
+      c1[4 * g] = b.x; c1[4 * g + 1] = b.y; c1[4 * g + 2] = b.z; c1[4 * g + 3] = b.w;
+    }
+  };
+  auto unpack = [&](const v16f &c0, const v16f &c1, unsigned mask, float2 (&x0)[8], float2 (&x1)[8]) {
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+      const bool in = (mask >> g) & 1u;
+      const bool i0 = v0 && in, i1 = v1 && in;
+      x0[2 * g] = i0 ? make_float2(c0[4 * g], c0[4 * g + 1]) : make_float2(0.f, 0.f);
+      x0[2 * g + 1] = i0 ? make_float2(c0[4 * g + 2], c0[4 * g + 3]) : make_float2(0.f, 0.f);
+      x1[2 * g] = i1 ? make_float2(c1[4 * g], c1[4 * g + 1]) : make_float2(0.f, 0.f);
+      x1[2 * g + 1] = i1 ? make_float2(c1[4 * g + 2], c1[4 * g + 3]) : make_float2(0.f, 0.f);
     }
   };
   const int STEPS = pxw / 32;
@@ -502,8 +518,11 @@ __global__ __launch_bounds__(256) void gram_partial_lp(const float2 *__restrict_
   if constexpr (FMT != kLpBF16) {
     float m0 = 0.f, m1 = 0.f;
     for (int j = 0; j < STEPS; ++j) {
+      v16f c0, c1;
+      unsigned mask;
+      load_raw(j, c0, c1, mask);
       float2 x0[8], x1[8];
-      load_step(j, x0, x1);
+      unpack(c0, c1, mask, x0, x1);
 #pragma unroll
       for (int e = 0; e < 8; ++e) {
         const float mr = sum16(x0[e].x + x1[e].x) * inv_nt, mi = sum16(x0[e].y + x1[e].y) * inv_nt;
@@ -529,9 +548,13 @@ __global__ __launch_bounds__(256) void gram_partial_lp(const float2 *__restrict_
   v4f S00 = {0.f, 0.f, 0.f, 0.f}, S01 = S00, S11 = S00, Q00 = S00, Q01 = S00, Q10 = S00, Q11 = S00;
   double2 a0 = make_double2(0.0, 0.0), a1 = a0;
   double mm = 0.0;
+  v16f h0, h1, n0, n1;
+  unsigned hmask = 0, nmask = 0;
+  load_raw(0, h0, h1, hmask);
   for (int j = 0; j < STEPS; ++j) {
+    load_raw(j + 1 < STEPS ? j + 1 : j, n0, n1, nmask);  // the last prefetch repeats the step
     float2 x0[8], x1[8];
-    load_step(j, x0, x1);
+    unpack(h0, h1, hmask, x0, x1);
     U r0h, i0h, r1h, i1h, r0l, i0l, r1l, i1l;
     float a0r = 0.f, a0i = 0.f, a1r = 0.f, a1i = 0.f, mmf = 0.f;
 #pragma unroll
@@ -583,6 +606,9 @@ __global__ __launch_bounds__(256) void gram_partial_lp(const float2 *__restrict_
     Q01 = prod(r0h, r0l, i1h, i1l, Q01);
     Q10 = prod(r1h, r1l, i0h, i0l, Q10);
     Q11 = prod(r1h, r1l, i1h, i1l, Q11);
+    h0 = n0;
+    h1 = n1;
+    hmask = nmask;
   }
 
   for (int i = tid; i < 2 * D * D; i += 256) red[i] = 0.0;
