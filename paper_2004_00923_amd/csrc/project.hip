@@ -265,7 +265,7 @@ struct PjOp<kPjFP8> {
 };
 
 template <int FMT, bool SPLIT>
-__global__ __launch_bounds__(256) void project_mfma(const float2 *__restrict__ H, int nt, long long npix,
+__global__ __launch_bounds__(256, 3) void project_mfma(const float2 *__restrict__ H, int nt, long long npix,
                                                     const double2 *__restrict__ V, KList kl,
                                                     float *__restrict__ image) {
   typedef PjOp<FMT> Op;
@@ -316,7 +316,14 @@ __global__ __launch_bounds__(256) void project_mfma(const float2 *__restrict__ H
         al[rt][j].e[e] = Alo[base + e];
       }
     }
-  // this lane's components (rows 16 rt + 4 g + r): a = 8 rt + 2 g + r / 2
+  // this lane's components (rows 16 rt + 4 g + r): a = 8 rt + 2 g + r / 2, with their
+  // column sums in registers (zero past the kept set, whose rows of A are zero too,
+  // so that those rows add nothing and the epilogue needs no branch)
+  float2 sv[4][2];
+#pragma unroll
+  for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+    for (int u = 0; u < 2; ++u) sv[rt][u] = ssum[8 * rt + 2 * g + u];
   // each wave takes a contiguous range of tiles, so that its 32 frame streams are read
   // sequentially (adjacent 128-byte lines from one tile to the next)
   const long long tiles = (npix + 15) / 16;
@@ -410,13 +417,10 @@ __global__ __launch_bounds__(256) void project_mfma(const float2 *__restrict__ H
     for (int rt = 0; rt < 4; ++rt)
 #pragma unroll
       for (int u = 0; u < 2; ++u) {
-        const int a = 8 * rt + 2 * g + u;
-        if (a < kl.n) {
-          const float2 s = ssum[a];
-          const float zr = acc[rt][2 * u] * inv + (mr * s.x - mi * s.y);
-          const float zi = acc[rt][2 * u + 1] * inv + (mr * s.y + mi * s.x);
-          e += zr * zr + zi * zi;
-        }
+        const float2 s = sv[rt][u];
+        const float zr = acc[rt][2 * u] * inv + (mr * s.x - mi * s.y);
+        const float zi = acc[rt][2 * u + 1] * inv + (mr * s.y + mi * s.x);
+        e += zr * zr + zi * zi;
       }
     e += __shfl_xor(e, 16);
     e += __shfl_xor(e, 32);
