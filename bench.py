@@ -480,21 +480,38 @@ def bench_batched8(args, hh, torch, dev):
                 del tws
         ws = hh.alloc_workspace(hh.batch_workspace_bytes(ps), dev)
         g = hh.Graph(ps, frames, imgs, ws)
+        stream = torch.cuda.current_stream()
         for _ in range(args.warmup):
-            g.launch()
+            g.launch(stream)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(args.steps):
-            g.launch()
+            g.launch(stream)
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
+        # each launch alone, bracketed by HIP events on the stream it is launched on
+        durs = []
+        for _ in range(min(args.steps, 20)):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            g.launch(stream)
+            b.record(stream)
+            b.synchronize()
+            durs.append(a.elapsed_time(b) * 1e-3)
         g.close()
         nfr = sum(nt for nt, _, _ in specs)
         npf = sum(nt * ny * nx for nt, ny, nx in specs)
+        # algorithmic bytes per launch: per px-frame 2 (frames) + 8 x 3 (H written once,
+        # read by the covariance and by the projection); per pixel 4 (image)
         byt = sum(nt * ny * nx * 26 + 4 * ny * nx for nt, ny, nx in specs)
+        launch_s = float(np.mean(durs))
+        gbs = byt / launch_s / 1e9
         forms[form] = {"interferograms_per_s": nfr * args.steps / el, "ms_per_launch": 1e3 * el / args.steps,
                        "px_frames_per_s": npf * args.steps / el,
-                       "hbm_frac": byt * args.steps / el / 1e9 / HBM_PEAK_GBS}
+                       "hbm_frac": byt * args.steps / el / 1e9 / HBM_PEAK_GBS,
+                       "roofline": {"bound": "hbm", "scope": "one graph launch (every kernel of the 8 stacks)",
+                                    "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
+                                    "traffic": None, "algorithmic_bytes": byt, "us_per_launch": 1e6 * launch_s}}
     f32 = forms["fp32"]
     out = {"metric": "interferograms/s through Fresnel+PCA, 8 uneven stacks per graph launch",
            "value": f32["interferograms_per_s"], "unit": "interferograms/s", "n_gpus": 1, "steps": args.steps,
@@ -503,6 +520,7 @@ def bench_batched8(args, hh, torch, dev):
            "config": {"workload": "8 uneven stacks (512^2x16, 1024^2x32, 2048x1024x64, 512^2x32, 1024^2x64, "
                                   "2048x1024x16, 512^2x64, 1024^2x16), seeds 0..7, PCs 2..nt-1, one HIP graph",
                       "interferograms_per_launch": sum(nt for nt, _, _ in specs)},
+           "roofline": f32["roofline"],
            "forms": forms,
            "tuning": {f"{k[0]} {k[3]}x{k[2]}x{k[1]}": v for k, v in tunings.items()}}
     print(json.dumps(out), flush=True)
