@@ -111,14 +111,29 @@ struct FftCfg {
   static constexpr int LDSN = fft_pad(N - 1) + 1;  // LDS slots per transform
 };
 
+// Exchange barrier of the passes below.  WAVE = false: the workgroup's barrier.
+// WAVE = true, for a transform held by exactly one wave in an LDS area of its own:
+// the LDS instructions of one wave are carried out in the order they are issued,
+// so a compiler-level barrier that keeps the writes before the reads suffices.
+template <bool WAVE>
+__device__ __forceinline__ void fft_sync() {
+  if constexpr (WAVE) {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+  } else {
+    __syncthreads();
+  }
+}
+
 // Passes P.. of the transform.  On entry v[i] holds element t + T*i of the
 // sequence entering pass P; on return v[i] = X[t + T*i] (natural order).
 // slot(e) maps a logical element of this transform to its LDS slot; every
-// thread of the workgroup must call this (it contains barriers).
+// thread of the workgroup must call this (it contains barriers; with WAVE every
+// thread of the wave, which must hold the whole transform).
 // SPLIT = false: lds holds float2 slots and each exchange moves whole complex
 // values.  SPLIT = true: lds holds float slots (half the LDS) and each exchange
 // moves the real parts, then the imaginary parts.
-template <int N, int EP, int P, bool SPLIT = false, class Slot, class L>
+template <int N, int EP, int P, bool SPLIT = false, bool WAVE = false, class Slot, class L>
 __device__ __forceinline__ void fft_passes(float2 (&v)[fft_e(N, EP)], int t, const float2 *__restrict__ tw,
                                            L *lds, Slot slot) {
   constexpr int E = FftCfg<N, EP>::E, T = FftCfg<N, EP>::T;
@@ -157,24 +172,24 @@ __device__ __forceinline__ void fft_passes(float2 (&v)[fft_e(N, EP)], int t, con
 #pragma unroll
           for (int k = 0; k < R; ++k) lds[slot(base + k * NS)] = half ? v[b + B * k].y : v[b + B * k].x;
         }
-        __syncthreads();
+        fft_sync<WAVE>();
         float w[E];
 #pragma unroll
         for (int i = 0; i < E; ++i) w[i] = lds[slot(t + T * i)];
-        __syncthreads();  // reads done before the next writes
+        fft_sync<WAVE>();  // reads done before the next writes
 #pragma unroll
         for (int i = 0; i < E; ++i) {
           if (half) v[i].y = w[i];
           else v[i].x = w[i];
         }
       }
-      fft_passes<N, EP, P + 1, SPLIT>(v, t, tw, lds, slot);
+      fft_passes<N, EP, P + 1, SPLIT, WAVE>(v, t, tw, lds, slot);
     } else {
-      __syncthreads();
+      fft_sync<WAVE>();
 #pragma unroll
       for (int i = 0; i < E; ++i) v[i] = lds[slot(t + T * i)];
-      if constexpr (P + 1 < FftCfg<N, EP>::P - 1) __syncthreads();  // reads done before the next pass writes
-      fft_passes<N, EP, P + 1, SPLIT>(v, t, tw, lds, slot);
+      if constexpr (P + 1 < FftCfg<N, EP>::P - 1) fft_sync<WAVE>();  // reads done before the next pass writes
+      fft_passes<N, EP, P + 1, SPLIT, WAVE>(v, t, tw, lds, slot);
     }
   }
 }

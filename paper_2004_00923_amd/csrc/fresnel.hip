@@ -69,6 +69,9 @@ __global__ __launch_bounds__(ROWS *(N / fft_e(N, EP))) void fresnel_rows(
     const void *__restrict__ src, const float *__restrict__ mean, int ny, const float2 *__restrict__ chirp_x,
     const float2 *__restrict__ chirp_y, const float2 *__restrict__ tw, float2 *__restrict__ out) {
   constexpr int E = FftCfg<N, EP>::E, T = FftCfg<N, EP>::T;
+  // a row is held by T <= 64 lanes of one wave, in an LDS area of its own: the
+  // exchanges need only the wave's own ordering (fft_sync)
+  constexpr bool kWave = T <= 64;
   const int t = threadIdx.x % T;
   const int r = threadIdx.x / T;
   const int row = blockIdx.x * ROWS + r;
@@ -115,7 +118,7 @@ __global__ __launch_bounds__(ROWS *(N / fft_e(N, EP))) void fresnel_rows(
       }
       stage8<(FftCfg<N, EP>::LDSN * sizeof(Slot)) % 16 == 0>(stage + 8 * c, x);
     }
-    __syncthreads();
+    fft_sync<kWave>();
 #pragma unroll
     for (int i = 0; i < E; ++i) {
       const int m = t + T * i;
@@ -123,8 +126,8 @@ __global__ __launch_bounds__(ROWS *(N / fft_e(N, EP))) void fresnel_rows(
       const float2 c = cmul(chirp_x[m], cy);
       v[i] = make_float2(val * c.x, val * c.y);
     }
-    __syncthreads();
-    fft_passes<N, EP, 0, SPLIT>(v, t, tw, lds + r * FftCfg<N, EP>::LDSN, RowSlot{});
+    fft_sync<kWave>();
+    fft_passes<N, EP, 0, SPLIT, kWave>(v, t, tw, lds + r * FftCfg<N, EP>::LDSN, RowSlot{});
   } else {
 #pragma unroll
     for (int i = 0; i < E; ++i) {
@@ -247,6 +250,9 @@ __global__ __launch_bounds__(ROWS *(N / fft_e(N, EP))) void fresnel_rows_persist
     const float2 *__restrict__ chirp_x, const float2 *__restrict__ chirp_y, const float2 *__restrict__ tw,
     float2 *__restrict__ out) {
   constexpr int E = FftCfg<N, EP>::E, T = FftCfg<N, EP>::T, L = N / 8 / T > 0 ? N / 8 / T : 1;
+  // a row is held by T <= 64 lanes of one wave, in an LDS area of its own: after the
+  // shared tables are loaded, the exchanges need only the wave's own ordering
+  constexpr bool kWave = T <= 64;
   static_assert(FftCfg<N, EP>::P > 1 && N / 8 >= T, "persistent rows need an LDS exchange and 8 pixels per thread");
   typedef typename std::conditional<SPLIT, float, float2>::type Slot;
   __shared__ __align__(16) Slot lds[ROWS * FftCfg<N, EP>::LDSN];
@@ -326,7 +332,7 @@ __global__ __launch_bounds__(ROWS *(N / fft_e(N, EP))) void fresnel_rows_persist
       }
       stage8<(FftCfg<N, EP>::LDSN * sizeof(Slot)) % 16 == 0>(stage + 8 * c, x);
     }
-    __syncthreads();
+    fft_sync<kWave>();
     float2 v[E];
 #pragma unroll
     for (int i = 0; i < E; ++i) {
@@ -334,13 +340,13 @@ __global__ __launch_bounds__(ROWS *(N / fft_e(N, EP))) void fresnel_rows_persist
       const float2 c = cmul(kTwLds ? cxp[tk + T * i] : cx[i], cy);
       v[i] = make_float2(val * c.x, val * c.y);
     }
-    __syncthreads();
-    fft_passes<N, EP, 0, SPLIT>(v, tk, twp, lds + r * FftCfg<N, EP>::LDSN, RowSlot{});
+    fft_sync<kWave>();
+    fft_passes<N, EP, 0, SPLIT, kWave>(v, tk, twp, lds + r * FftCfg<N, EP>::LDSN, RowSlot{});
     if (live) {
 #pragma unroll
       for (int i = 0; i < E; ++i) out[base + tk + T * i] = v[i];
     }
-    __syncthreads();  // the LDS is reused by the next item
+    fft_sync<kWave>();  // the LDS is reused by the next item
 #pragma unroll
     for (int l = 0; l < L; ++l) cur[l] = nxt[l];
     live = live2;
