@@ -170,10 +170,13 @@ struct Row1 {
 };
 
 // Q-point transform of this thread's frame slot of one unit, staged afterwards
-// by the caller.  Shared by passes 2 and 3 so that both see the same H.
+// by the caller.  Shared by passes 2 and 3 so that both see the same H.  A frame's
+// T = Q / 16 <= 64 threads lie in one wave and exchange through the frame's own LDS
+// area, so the exchanges need only the wave's own ordering.
 template <int Q>
 __device__ __forceinline__ void quarter_fft(float2 (&v)[16], int t, const float2 *tws, float *xch, int f) {
-  fft_passes<Q, 16, 0, true>(v, t, tws, xch + f * QCfg<Q>::LDSN, Row1{});
+  static_assert(QCfg<Q>::T <= 64, "a frame's transform within one wave");
+  fft_passes<Q, 16, 0, true, true>(v, t, tws, xch + f * QCfg<Q>::LDSN, Row1{});
 }
 
 template <int Q, bool PF>

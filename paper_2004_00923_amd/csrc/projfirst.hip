@@ -187,8 +187,12 @@ __global__ __launch_bounds__(kPfThreads) void proj_rows(const uint16_t *__restri
 #pragma unroll
     for (int i = 0; i < E; ++i) v[i] = live ? jb[r * LDSN + fft_pad(t + T * i)] : make_float2(0.f, 0.f);
     if constexpr (FftCfg<N, 16>::P > 1) {
-      __syncthreads();  // every staged value is in registers before the exchanges reuse the rows
-      fft_passes<N, 16, 0, false>(v, t, tw, jb + r * LDSN, PfRowSlot{});
+      // every staged value of row r is in registers before the exchanges reuse that row;
+      // only this transform reads and writes row r, so when its T <= 64 threads lie in
+      // one wave the wave's own ordering suffices
+      constexpr bool kWave = T <= 64;
+      fft_sync<kWave>();
+      fft_passes<N, 16, 0, false, kWave>(v, t, tw, jb + r * LDSN, PfRowSlot{});
     } else {
       fft_passes<N, 16, 0, false>(v, t, tw, (float2 *)nullptr, PfRowSlot{});
     }
