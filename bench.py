@@ -566,6 +566,27 @@ def bench_serve(args, hh, torch, dev):
             gbs = sum(v[n]["windows_per_s"] * win_bytes[n] for n in ("A", "B")) / 1e9
             v["roofline"] = {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                              "frac": gbs / HBM_PEAK_GBS, "bytes_per_window": win_bytes}
+    # the FFT row of Table 1: one 32-frame window per frame (hop 1) of a 1024^2 camera
+    # at 500 frames/s, demodulated by the temporal DFT (Eqs. (8)-(9), band 8..24 of the
+    # paper = 0-based 7..23): paced for latency, then unthrottled for the sustained rate
+    fspec = CameraSpec("F", 1024, 1024, 500.0, 100, hop=1, k_lo=7, k_hi=23, demod="fourier", ring_hops=96)
+    fourier = {}
+    for paced, wf in ((True, 250), (False, 1000)):
+        srv = Server(hbm_budget_bytes=64 << 30, device=dev)
+        srv.admit(fspec, src["A"])
+        print(f"bench: serve fourier hop 1 {'paced' if paced else 'unthrottled'}", file=sys.stderr, flush=True)
+        srv.run({"F": 8}, paced=False)   # warm-up
+        r = srv.run({"F": wf}, paced=paced)
+        sm = summarize(r, [fspec])["F"]
+        # output voxels: the window's 32 holograms demodulated per output image
+        sm["output_gvoxel_per_s"] = sm["windows_per_s"] * 32 * 1024 * 1024 / 1e9
+        # algorithmic bytes per output: one new frame read as uint16 and written as a
+        # hologram, the window's 32 holograms read once, the image
+        fb = 1024 * 1024 * (2 + 8 + 32 * 8 + 4)
+        gbs = sm["windows_per_s"] * fb / 1e9
+        sm["roofline"] = {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                          "frac": gbs / HBM_PEAK_GBS, "bytes_per_window": fb}
+        fourier["paced" if paced else "unthrottled"] = sm
     out = {"metric": "frame-to-image latency p99 (ms), camera A 1024^2 at 500 frames/s, with camera B",
            "value": a["p99_ms"], "unit": "ms", "n_gpus": 1, "steps": 40, "warmup": 4,
            "ms_per_step": a["p50_ms"], "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
@@ -575,7 +596,8 @@ def bench_serve(args, hh, torch, dev):
            "sustained_windows_per_s": {k: v["A"]["windows_per_s"] + v["B"]["windows_per_s"]
                                        for k, v in res.items() if k.endswith("unthrottled")},
            "roofline": res["fp32_unthrottled"]["roofline"],
-           "serve": res}
+           "serve": res,
+           "fourier_hop1": fourier}
     print(json.dumps(out), flush=True)
 
 

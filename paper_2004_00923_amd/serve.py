@@ -10,6 +10,11 @@ every window whose frames have all been transformed is analysed (steps
 hh_analyze_batch call, which solves all their eigenproblems in one launch
 (continuous batching across cameras).
 
+A camera may instead demodulate by the temporal Fourier transform (Eqs. (8)-(9),
+the paper's comparison method, `demod="fourier"`): each window's image is the
+power in a band of temporal frequencies (hh_fourier_render, no covariance or
+eigenproblem), typically at hop 1, one image per frame (the FFT row of Table 1).
+
 Ring layout (per camera).  The hologram ring has R + M slots, R a multiple of
 `hop` and M = max(window - hop, 0).  Frame k lands in slot k mod R, and again in
 slot R + (k mod R) when k mod R < M.  Window c (frames c*hop .. c*hop+window-1)
@@ -62,6 +67,8 @@ class CameraSpec:
     pitch_m: float = 20e-6
     ring_hops: int = 6               # frame ring of ring_hops * hop frames (>= one window): how
                                      # far frames may run ahead of the oldest pending window
+    demod: str = "pca"               # "pca": Eqs. (4)-(7), components k_lo..k_hi; "fourier": Eqs. (8)-(9),
+                                     # temporal frequencies k_lo..k_hi (0-based)
 
     def ring(self) -> "RingPlan":
         return RingPlan(self.window, self.hop, self.ring_hops)
@@ -247,6 +254,8 @@ def camera_bytes(spec: CameraSpec, ring: RingPlan, image_buffers: int,
     ws = hh.analyze_batch_workspace_bytes([spec.params()] * batch_per_camera)
     if ws == 0:
         raise ValueError(f"camera {spec.name}: parameters rejected by the library")
+    if spec.demod == "fourier":
+        ws = 0   # the Fourier image needs no workspace
     return {"frames": ring.R * npix * 2, "holo": ring.slots * npix * 8, "images": image_buffers * npix * 4,
             "workspace": ws}
 
@@ -339,6 +348,8 @@ class Server:
         if spec.precision in ("fp16store", "exact"):
             raise ValueError(f"camera {spec.name}: the rings hold FP32 holograms; form {spec.precision} "
                              "starts from frames and does not apply")
+        if spec.demod not in ("pca", "fourier"):
+            raise ValueError(f"camera {spec.name}: demod must be 'pca' or 'fourier', not {spec.demod!r}")
         if any(c.spec.name == spec.name for c in self.cams) or any(r.spec.name == spec.name for r in self.pending):
             raise ValueError(f"camera {spec.name}: name already in use")
 
@@ -430,14 +441,20 @@ class Server:
     def _analyse(self, ready, records):
         import torch
         by_name = {c.spec.name: c for c in self.cams}
-        ps, holos, imgs = [], [], []
+        ps, holos, pimgs, imgs = [], [], [], []
         for name, c in ready:
             cam = by_name[name]
             s = cam.ring.window_slot(c)
-            ps.append(cam.p)
-            holos.append(cam.holo[s:s + cam.spec.window])
-            imgs.append(cam.images[c % len(cam.images)])
-        hh.hh_analyze_batch(ps, holos, imgs, self.ws, stream=self.compute_stream)
+            img = cam.images[c % len(cam.images)]
+            imgs.append(img)
+            if cam.spec.demod == "fourier":   # Eqs. (8)-(9): no covariance, no eigenproblem
+                hh.hh_fourier_render(cam.p, cam.holo[s:s + cam.spec.window], img, stream=self.compute_stream)
+            else:
+                ps.append(cam.p)
+                holos.append(cam.holo[s:s + cam.spec.window])
+                pimgs.append(img)
+        if ps:
+            hh.hh_analyze_batch(ps, holos, pimgs, self.ws, stream=self.compute_stream)
         done = torch.cuda.Event(enable_timing=True)
         done.record(self.compute_stream)
         with torch.cuda.stream(self.compute_stream):

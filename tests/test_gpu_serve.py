@@ -211,3 +211,35 @@ def test_serve_gaps_and_disconnect(hh):
         idx = [(c * A.hop + j) % n_src for j in range(A.window)]
         r = oracle.pipeline_ref(frames[idx], LAM, Z, PITCH, 2, 31)
         assert rel(to_np(srv.kept[("A", c)]), r["image"]) <= IMG_TOL
+
+
+def test_serve_fourier_hop1_vs_oracle_and_mixed(hh):
+    # the Table 1 FFT row as a stream: a 32-frame window every frame (hop 1),
+    # Eqs. (8)-(9) with the paper's band n1..n2 = 8..24 (0-based 7..23); each image
+    # against the oracle's Fourier image of that window, and equal alone and beside
+    # a PCA camera
+    from paper_2004_00923_amd.serve import CameraSpec
+    F = CameraSpec("F", 64, 128, 500.0, 120, hop=1, k_lo=7, k_hi=23, demod="fourier", ring_hops=48)
+    A = CameraSpec("A", 128, 128, 500.0, 100)
+    n_src = 48
+    src = {"F": _source(F.seed, n_src, F.ny, F.nx), "A": _source(A.seed, n_src, A.ny, A.nx)}
+    wf, wa = 12, 3
+    keepF = [("F", c) for c in range(wf)]
+    say("serve: Fourier camera alone, hop 1, unthrottled")
+    alone, res_a = _serve([F], src, {"F": wf}, False, keepF)
+    say("serve: Fourier camera beside a PCA camera, paced")
+    mix, res_m = _serve([F, A], src, {"F": wf, "A": wa}, True, keepF + [("A", c) for c in range(wa)])
+    assert res_a["cameras"]["F"]["analysed"] == wf and res_m["cameras"]["A"]["analysed"] == wa
+    frames = src["F"][0]
+    for c in range(wf):
+        a = to_np(alone.kept[("F", c)])
+        assert np.array_equal(a, to_np(mix.kept[("F", c)])), f"F window {c}: mixed differs from alone"
+        idx = [(c + j) % n_src for j in range(F.window)]
+        r = oracle.fourier_render_ref(oracle.fresnel_ref(frames[idx], LAM, Z, PITCH), 7, 23)
+        e = rel(a, r)
+        assert e <= IMG_TOL, f"F window {c}: {e:.2e}"
+    frames_a = src["A"][0]
+    for c in range(wa):
+        idx = [(c * A.hop + j) % n_src for j in range(A.window)]
+        r = oracle.pipeline_ref(frames_a[idx], LAM, Z, PITCH, 2, 31)
+        assert rel(to_np(mix.kept[("A", c)]), r["image"]) <= IMG_TOL, f"A window {c}"

@@ -209,3 +209,13 @@ def test_admission_release_and_queued_request():
     assert [(i, c) for _, i, c in wins] == [("A", 0), ("A", 1), ("A", 2), ("B", 0), ("B", 1)]
     admit_b = [o for o in order if o[0] == "admit"][0]
     assert admit_b[2] > 1 and adm.held == {"B": need_b}
+
+
+def test_fourier_camera_needs_no_analysis_workspace():
+    from paper_2004_00923_amd.serve import CameraSpec, camera_bytes
+    P = CameraSpec("P", 64, 64, 500.0, 1)
+    F = CameraSpec("F", 64, 64, 500.0, 1, hop=1, k_lo=7, k_hi=23, demod="fourier", ring_hops=64)
+    assert camera_bytes(P, P.ring(), 4)["workspace"] > 0
+    b = camera_bytes(F, F.ring(), 4)
+    assert b["workspace"] == 0
+    assert F.ring().R == 64 and F.ring().slots == 64 + 31
