@@ -32,6 +32,7 @@ METRIC = "interferograms/s through Fresnel+PCA (1024^2, 32-frame); % HBM rooflin
 NT, NY, NX, K_LO, K_HI = 32, 1024, 1024, 2, 31
 LAM, PITCH, Z = 785e-9, 20e-6, 0.3
 HBM_PEAK_GBS = 8000.0
+PCIE_PEAK_GBS = 64.0   # host link, one direction (PCIe 5.0 x16)
 PAPER_INTERFEROGRAMS_PER_S = 20 * 32  # PCA of 32-frame stacks "up to 20 times per second" (Titan RTX)
 PACED_STACKS_PER_S = 20.0  # 500 frames/s, a 32-frame window every 25 frames
 
@@ -561,11 +562,16 @@ def bench_serve(args, hh, torch, dev):
     hop, win = 25, 32
     win_bytes = {"A": 1024 * 1024 * (hop * (2 + 8) + win * 8 * 2 + 4),
                  "B": 2048 * 1024 * (hop * (2 + 8) + win * 8 * 2 + 4)}
+    # frames enter over the host link: each window brings `hop` new uint16 frames
+    in_bytes = {"A": 1024 * 1024 * 2 * hop, "B": 2048 * 1024 * 2 * hop}
     for k, v in res.items():
         if k.endswith("unthrottled"):
             gbs = sum(v[n]["windows_per_s"] * win_bytes[n] for n in ("A", "B")) / 1e9
             v["roofline"] = {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                              "frac": gbs / HBM_PEAK_GBS, "bytes_per_window": win_bytes}
+            ing = sum(v[n]["windows_per_s"] * in_bytes[n] for n in ("A", "B")) / 1e9
+            v["ingest"] = {"bound": "host link (PCIe 5.0 x16)", "achieved": ing, "peak": PCIE_PEAK_GBS,
+                           "unit": "GB/s", "frac": ing / PCIE_PEAK_GBS, "bytes_per_window": in_bytes}
     # the FFT row of Table 1: one 32-frame window per frame (hop 1) of a 1024^2 camera
     # at 500 frames/s, demodulated by the temporal DFT (Eqs. (8)-(9), band 8..24 of the
     # paper = 0-based 7..23): paced for latency, then unthrottled for the sustained rate
@@ -596,6 +602,7 @@ def bench_serve(args, hh, torch, dev):
            "sustained_windows_per_s": {k: v["A"]["windows_per_s"] + v["B"]["windows_per_s"]
                                        for k, v in res.items() if k.endswith("unthrottled")},
            "roofline": res["fp32_unthrottled"]["roofline"],
+           "ingest": res["fp32_unthrottled"]["ingest"],
            "serve": res,
            "fourier_hop1": fourier}
     print(json.dumps(out), flush=True)
