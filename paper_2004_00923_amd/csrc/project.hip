@@ -270,12 +270,13 @@ __global__ __launch_bounds__(256, 3) void project_mfma(const float2 *__restrict_
                                                     float *__restrict__ image) {
   typedef PjOp<FMT> Op;
   typedef typename Op::elt elt;
+  typedef typename Op::vec vec;
   union Frag {
-    typename Op::vec v;
+    vec v;
     elt e[8];
   };
   constexpr float kAScale = FMT == kPjFP8 ? 256.f : 1.f;
-  __shared__ elt Ahi[64 * 64], Alo[64 * 64];
+  __shared__ __align__(16) elt Ahi[64 * 64], Alo[64 * 64];
   __shared__ float2 ssum[32];
   const int tid = threadIdx.x, lane = tid & 63;
   const int n = lane & 15, g = lane >> 4;
@@ -304,65 +305,55 @@ __global__ __launch_bounds__(256, 3) void project_mfma(const float2 *__restrict_
     ssum[tid] = make_float2((float)sr, (float)si);
   }
   __syncthreads();
-  Frag ah[4][2], al[4][2];
-#pragma unroll
-  for (int rt = 0; rt < 4; ++rt)
-#pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      const int base = (16 * rt + n) * 64 + 32 * j + 8 * g;
-#pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        ah[rt][j].e[e] = Ahi[base + e];
-        al[rt][j].e[e] = Alo[base + e];
-      }
-    }
   // this lane's components (rows 16 rt + 4 g + r): a = 8 rt + 2 g + r / 2, with their
   // column sums in registers (zero past the kept set, whose rows of A are zero too,
-  // so that those rows add nothing and the epilogue needs no branch)
+  // so that those rows add nothing and the epilogue needs no branch); the A
+  // fragments are read from LDS where they are used (one 8-element vector each)
   float2 sv[4][2];
 #pragma unroll
   for (int rt = 0; rt < 4; ++rt)
 #pragma unroll
     for (int u = 0; u < 2; ++u) sv[rt][u] = ssum[8 * rt + 2 * g + u];
-  // each wave takes a contiguous range of tiles, so that its 32 frame streams are read
-  // sequentially (adjacent 128-byte lines from one tile to the next)
-  const long long tiles = (npix + 15) / 16;
-  const long long waves = (long long)gridDim.x * 4, per = (tiles + waves - 1) / waves;
+  int an = n;  // made opaque per pair below (BF16, FP16), so that the fragment reads are not hoisted
+              // into registers
+  auto afrag = [&](const elt *A, int rt, int j) {
+    return *reinterpret_cast<const vec *>(A + (16 * rt + an) * 64 + 32 * j + 8 * g);
+  };
+  // Two 16-pixel tiles at a time: lane (n, g) loads pixels 2n and 2n + 1 of the pair
+  // (one 16-byte load per frame), which are column n of the first and of the second
+  // tile.  Each wave takes a contiguous range of pairs, so that its 32 frame streams
+  // are read sequentially.  npix is a multiple of 64: every pair is whole.
+  const long long pairs = npix / 32;
+  const long long waves = (long long)gridDim.x * 4, per = (pairs + waves - 1) / waves;
   const long long t_begin = ((long long)blockIdx.x * 4 + (tid >> 6)) * per;
-  const long long t_end = t_begin + per < tiles ? t_begin + per : tiles;
-  // the eight frames of this lane for one tile; the next tile's are loaded before
-  // this tile is converted and multiplied (unconditional loads from a valid address)
-  auto load = [&](long long tl, float2 (&d)[2][4]) {
-    const long long pc = tl < t_end && tl * 16 + n < npix ? tl * 16 + n : 0;
+  const long long t_end = t_begin + per < pairs ? t_begin + per : pairs;
+  // the eight frames of this lane for one pair; the next pair's are loaded before
+  // this pair is converted and multiplied (unconditional loads from a valid address)
+  auto load = [&](long long tp, float4 (&d)[2][4]) {
+    const long long pc = tp < t_end ? tp * 32 + 2 * n : 0;
 #pragma unroll
     for (int j = 0; j < 2; ++j)
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const int t = 16 * j + 4 * g + i;
-        d[j][i] = H[(long long)(t < nt ? t : 0) * npix + pc];
+        d[j][i] = *reinterpret_cast<const float4 *>(H + (long long)(t < nt ? t : 0) * npix + pc);
       }
   };
-  float2 nx_[2][4];
-  load(t_begin, nx_);
-  for (long long tile = t_begin; tile < t_end; ++tile) {
-    const long long p = tile * 16 + n;
-    const bool live = p < npix;
+  // one tile: the pixel's temporal mean split off, the per-pixel scale, the MFMA
+  // products, the |.|^2 sum over the components (all four lanes of the pixel get it)
+  auto tile = [&](const float2 (&hin)[2][4]) {
     float2 h[2][4];
-#pragma unroll
-    for (int j = 0; j < 2; ++j)
-#pragma unroll
-      for (int i = 0; i < 4; ++i) h[j][i] = nx_[j][i];
-    load(tile + 1, nx_);
-    // m: the pixel's temporal mean (the four lanes of the pixel hold eight frames each)
     float mr = 0.f, mi = 0.f;
 #pragma unroll
     for (int j = 0; j < 2; ++j)
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
+      for (int i = 0; i < 4; ++i) {
+        h[j][i] = hin[j][i];
         if (16 * j + 4 * g + i < nt) {
           mr += h[j][i].x;
           mi += h[j][i].y;
         }
+      }
     mr += __shfl_xor(mr, 16);
     mi += __shfl_xor(mi, 16);
     mr += __shfl_xor(mr, 32);
@@ -400,39 +391,55 @@ __global__ __launch_bounds__(256, 3) void project_mfma(const float2 *__restrict_
           bh[j].e[2 * i + q] = hi;
           if constexpr (SPLIT) bl[j].e[2 * i + q] = Op::cvt(x - Op::back(hi));
         }
-    pv4f acc[4];
-#pragma unroll
-    for (int rt = 0; rt < 4; ++rt) {
-      acc[rt] = pv4f{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-      for (int j = 0; j < 2; ++j) {
-        acc[rt] = Op::mma(ah[rt][j].v, bh[j].v, acc[rt]);
-        acc[rt] = Op::mma(al[rt][j].v, bh[j].v, acc[rt]);
-        if constexpr (SPLIT) acc[rt] = Op::mma(ah[rt][j].v, bl[j].v, acc[rt]);
-      }
-    }
     const float inv = 1.f / (sc * kAScale);  // powers of two: exact
     float e = 0.f;
 #pragma unroll
-    for (int rt = 0; rt < 4; ++rt)
+    for (int rt = 0; rt < 4; ++rt) {
+      pv4f acc = pv4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        acc = Op::mma(afrag(Ahi, rt, j), bh[j].v, acc);
+        acc = Op::mma(afrag(Alo, rt, j), bh[j].v, acc);
+        if constexpr (SPLIT) acc = Op::mma(afrag(Ahi, rt, j), bl[j].v, acc);
+      }
 #pragma unroll
       for (int u = 0; u < 2; ++u) {
         const float2 s = sv[rt][u];
-        const float zr = acc[rt][2 * u] * inv + (mr * s.x - mi * s.y);
-        const float zi = acc[rt][2 * u + 1] * inv + (mr * s.y + mi * s.x);
+        const float zr = acc[2 * u] * inv + (mr * s.x - mi * s.y);
+        const float zi = acc[2 * u + 1] * inv + (mr * s.y + mi * s.x);
         e += zr * zr + zi * zi;
       }
+    }
     e += __shfl_xor(e, 16);
     e += __shfl_xor(e, 32);
-    if (g == 0 && live) image[p] = e;
+    return e;
+  };
+  float4 nx_[2][4];
+  load(t_begin, nx_);
+  for (long long tp = t_begin; tp < t_end; ++tp) {
+    float2 h0[2][4], h1[2][4];
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        h0[j][i] = make_float2(nx_[j][i].x, nx_[j][i].y);
+        h1[j][i] = make_float2(nx_[j][i].z, nx_[j][i].w);
+      }
+    load(tp + 1, nx_);
+    an = n;
+    if constexpr (FMT != kPjFP8) asm volatile("" : "+v"(an));  // FP8 fragments (8 bytes) stay in registers
+    const float e0 = tile(h0);
+    __builtin_amdgcn_sched_barrier(0);  // one tile's work at a time (registers)
+    const float e1 = tile(h1);
+    if (g == 0) *reinterpret_cast<float2 *>(image + tp * 32 + 2 * n) = make_float2(e0, e1);
   }
 }
 
 template <int FMT, bool SPLIT>
 hipError_t launch_pmfma(const float2 *H, int nt, long long npix, const double2 *V, const KList &kl, float *image,
                         hipStream_t s) {
-  const long long tiles = (npix + 15) / 16;
-  long long groups = (tiles + 31) / 32;  // about eight tiles per wave
+  const long long pairs = npix / 32;      // pairs of 16-pixel tiles (npix is a multiple of 64)
+  long long groups = (pairs + 15) / 16;  // about four pairs per wave
   if (groups < 1) groups = 1;
   if (groups > 4096) groups = 4096;
   hipLaunchKernelGGL((project_mfma<FMT, SPLIT>), dim3((unsigned)groups), dim3(256), 0, s, H, nt, npix, V, kl, image);
