@@ -276,7 +276,10 @@ __global__ __launch_bounds__(256, 3) void project_mfma(const float2 *__restrict_
     elt e[8];
   };
   constexpr float kAScale = FMT == kPjFP8 ? 256.f : 1.f;
-  __shared__ __align__(16) elt Ahi[64 * 64], Alo[64 * 64];
+  // rows padded to 72 elements: the 16 lanes of an LDS phase (rows n, 16-byte fragments)
+  // then fall on distinct banks
+  constexpr int LA = 72;
+  __shared__ __align__(16) elt Ahi[64 * LA], Alo[64 * LA];
   __shared__ float2 ssum[32];
   const int tid = threadIdx.x, lane = tid & 63;
   const int n = lane & 15, g = lane >> 4;
@@ -291,8 +294,8 @@ __global__ __launch_bounds__(256, 3) void project_mfma(const float2 *__restrict_
       x = (float)(pp == 0 ? v.x : pp == 1 ? -v.y : pp == 2 ? v.y : v.x) * kAScale;
     }
     const elt h = Op::cvt(x);
-    Ahi[i] = h;
-    Alo[i] = Op::cvt(x - Op::back(h));
+    Ahi[c * LA + kk] = h;
+    Alo[c * LA + kk] = Op::cvt(x - Op::back(h));
   }
   if (tid < 32) {
     double sr = 0.0, si = 0.0;
@@ -317,7 +320,7 @@ __global__ __launch_bounds__(256, 3) void project_mfma(const float2 *__restrict_
   int an = n;  // made opaque per pair below (BF16, FP16), so that the fragment reads are not hoisted
               // into registers
   auto afrag = [&](const elt *A, int rt, int j) {
-    return *reinterpret_cast<const vec *>(A + (16 * rt + an) * 64 + 32 * j + 8 * g);
+    return *reinterpret_cast<const vec *>(A + (16 * rt + an) * LA + 32 * j + 8 * g);
   };
   // Two 16-pixel tiles at a time: lane (n, g) loads pixels 2n and 2n + 1 of the pair
   // (one 16-byte load per frame), which are column n of the first and of the second
