@@ -441,10 +441,12 @@ __global__ __launch_bounds__(256, 3) void project_mfma(const float2 *__restrict_
 template <int FMT, bool SPLIT>
 hipError_t launch_pmfma(const float2 *H, int nt, long long npix, const double2 *V, const KList &kl, float *image,
                         hipStream_t s) {
+  // every group builds the operand table of the kept components first: about sixteen
+  // pairs of tiles per wave amortise it (at most 512 groups, two per compute unit)
   const long long pairs = npix / 32;      // pairs of 16-pixel tiles (npix is a multiple of 64)
-  long long groups = (pairs + 15) / 16;  // about four pairs per wave
+  long long groups = (pairs + 63) / 64;
   if (groups < 1) groups = 1;
-  if (groups > 4096) groups = 4096;
+  if (groups > 512) groups = 512;
   hipLaunchKernelGGL((project_mfma<FMT, SPLIT>), dim3((unsigned)groups), dim3(256), 0, s, H, nt, npix, V, kl, image);
   return hipGetLastError();
 }
