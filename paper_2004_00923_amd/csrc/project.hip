@@ -451,6 +451,120 @@ hipError_t launch_pmfma(const float2 *H, int nt, long long npix, const double2 *
   return hipGetLastError();
 }
 
+// FP32 direct projection, Eq. (6) as written (the kept components, no complement),
+// on v_mfma_f32_32x32x2f32: D[c][n] = sum_kk A[c][kk] B[kk][n] with rows c = 2a + part
+// (component a of the kept list), columns n = 32 pixels, kk = 2t + part over the
+// frames, A the real 2x2 form of V[t][k_a] and B = H minus the pixel's temporal mean
+// m (the mean's contribution m s_a, s_a = sum_t V[t][k_a], is added in the epilogue,
+// as in the low-precision forms).  Lane (j, h) of a wave holds pixel j of the tile:
+// all its frames (the two lanes j and 32 + j load the same 8 bytes), the real parts
+// as B operand for h = 0, the imaginary parts for h = 1.  RB row blocks of 32: one
+// when at most 16 components are kept (the direct mode chosen automatically), two
+// for up to 32.  n_t <= 32.
+__device__ __forceinline__ int acc32_row(int lane, int r) { return 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3); }
+
+typedef float pv16f __attribute__((ext_vector_type(16)));
+
+template <int RB>
+__global__ __launch_bounds__(256, 2) void project_mfma32(const float2 *__restrict__ H, int nt, long long npix,
+                                                      const double2 *__restrict__ V, KList kl,
+                                                      float *__restrict__ image) {
+  __shared__ float Af[64 * 65];
+  __shared__ float2 ssum[32];
+  const int tid = threadIdx.x, lane = tid & 63, j = lane & 31, h = lane >> 5;
+  for (int i = tid; i < 64 * 64; i += 256) {
+    const int c = i >> 6, kk = i & 63, a = c >> 1, t = kk >> 1;
+    float x = 0.f;
+    if (a < kl.n && t < nt) {
+      const double2 v = V[t * nt + kl.k[a]];
+      const int pp = ((c & 1) << 1) | (kk & 1);
+      x = (float)(pp == 0 ? v.x : pp == 1 ? -v.y : pp == 2 ? v.y : v.x);
+    }
+    Af[c * 65 + kk] = x;
+  }
+  if (tid < 32) {
+    double sr = 0.0, si = 0.0;
+    if (tid < kl.n)
+      for (int t = 0; t < nt; ++t) {
+        const double2 v = V[t * nt + kl.k[tid]];
+        sr += v.x;
+        si += v.y;
+      }
+    ssum[tid] = make_float2((float)sr, (float)si);
+  }
+  __syncthreads();
+  // A operand of K-step s for row block rb: A[32 rb + j][2 s + h]
+  float av[RB][32];
+#pragma unroll
+  for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+    for (int s = 0; s < 32; ++s) av[rb][s] = Af[(32 * rb + j) * 65 + 2 * s + h];
+  // this lane's components: rows 32 rb + 8 q + 4 h + u, u = 0..3 -> components
+  // 16 rb + 4 q + 2 h (u = 0, 1) and that + 1 (u = 2, 3); their column sums
+  float2 sv[RB][4][2];
+#pragma unroll
+  for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int u = 0; u < 2; ++u) sv[rb][q][u] = ssum[16 * rb + 4 * q + 2 * h + u];
+  const float inv_nt = 1.f / (float)nt;
+  const long long tiles = npix / 32;  // npix is a multiple of 64
+  for (long long tl = blockIdx.x * 4 + (tid >> 6); tl < tiles; tl += (long long)gridDim.x * 4) {
+    const long long p = tl * 32 + j;
+    float2 x[32];
+#pragma unroll
+    for (int t = 0; t < 32; ++t) x[t] = H[(long long)(t < nt ? t : 0) * npix + p];
+    float mr = 0.f, mi = 0.f;
+#pragma unroll
+    for (int t = 0; t < 32; ++t)
+      if (t < nt) {
+        mr += x[t].x;
+        mi += x[t].y;
+      }
+    mr *= inv_nt;
+    mi *= inv_nt;
+    pv16f acc[RB];
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[rb][r] = 0.f;
+#pragma unroll
+    for (int s = 0; s < 32; ++s) {
+      const float b = s < nt ? (h ? x[s].y - mi : x[s].x - mr) : 0.f;
+#pragma unroll
+      for (int rb = 0; rb < RB; ++rb) acc[rb] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[rb][s], b, acc[rb], 0, 0, 0);
+    }
+    float e = 0.f;
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+          const float2 sa = sv[rb][q][u];
+          const float zr = acc[rb][4 * q + 2 * u] + (mr * sa.x - mi * sa.y);
+          const float zi = acc[rb][4 * q + 2 * u + 1] + (mr * sa.y + mi * sa.x);
+          e += zr * zr + zi * zi;
+        }
+    e += __shfl_xor(e, 32);
+    if (h == 0) image[p] = e;
+  }
+}
+
+hipError_t launch_pmfma32(const float2 *H, int nt, long long npix, const double2 *V, const KList &kl, float *image,
+                          hipStream_t s) {
+  const long long tiles = npix / 32;
+  long long groups = (tiles + 31) / 32;  // about eight tiles per wave
+  if (groups < 1) groups = 1;
+  if (groups > 1024) groups = 1024;
+  if (kl.n <= 16)
+    hipLaunchKernelGGL((project_mfma32<1>), dim3((unsigned)groups), dim3(256), 0, s, H, nt, npix, V, kl, image);
+  else
+    hipLaunchKernelGGL((project_mfma32<2>), dim3((unsigned)groups), dim3(256), 0, s, H, nt, npix, V, kl, image);
+  return hipGetLastError();
+}
+
 // kept / dropped component lists of the selector I_f
 bool select_list(int nt, int k_lo, int k_hi, int mode, KList &kl) {
   const int kept = k_hi - k_lo + 1, dropped = nt - kept;
@@ -497,6 +611,10 @@ hipError_t launch_project(const float2 *holo, int nt, long long npix, const doub
   const double2 *V2 = reinterpret_cast<const double2 *>(V);
   float2 *img = reinterpret_cast<float2 *>(image);
   if (complement) return launch_k<true>(kl.n, H, nt, npair, V2, kl, img, s, "project_complement");
+  if (nt <= 32 && npix % 64 == 0) {  // the kept components on FP32 MFMA
+    ProfScope ps("project_direct", s);
+    return launch_pmfma32(holo, nt, npix, V2, kl, image, s);
+  }
   return launch_k<false>(kl.n, H, nt, npair, V2, kl, img, s, "project_direct");
 }
 
