@@ -238,7 +238,10 @@ __global__ __launch_bounds__(256) void gram_partial16(const float2 *__restrict__
 }
 
 // 32 < n_t <= 64 path on v_mfma_f32_32x32x2f32: lane (fr, half) holds frames fr and
-// 32 + fr; the two half-waves take one half of the wave's pixels each.
+// 32 + fr; the two half-waves take one half of the wave's pixels each.  MEAN: the
+// reference is the temporal mean (a 32-lane sum); else frame 0's value, read from
+// lane 0 of each half-wave.
+template <bool MEAN>
 __global__ __launch_bounds__(256, 2) void gram_partial64(const float2 *__restrict__ H, int nt, long long npix,
                                                       int pxw, double *__restrict__ partial) {
   constexpr int D = 64;
@@ -302,7 +305,18 @@ __global__ __launch_bounds__(256, 2) void gram_partial64(const float2 *__restric
         float2 x[2];
         x[0] = (in && valid[0]) ? make_float2(h0[4 * g + 2 * e], h0[4 * g + 2 * e + 1]) : make_float2(0.f, 0.f);
         x[1] = (in && valid[1]) ? make_float2(h1[4 * g + 2 * e], h1[4 * g + 2 * e + 1]) : make_float2(0.f, 0.f);
-        const float mr = sum32(x[0].x + x[1].x) * inv_nt, mi = sum32(x[0].y + x[1].y) * inv_nt;
+        float mr, mi;
+        if constexpr (MEAN) {
+          mr = sum32(x[0].x + x[1].x) * inv_nt;
+          mi = sum32(x[0].y + x[1].y) * inv_nt;
+        } else {  // lanes 0 and 32 hold frame 0 of their half-wave's pixel
+          const int lo_r = __builtin_amdgcn_readlane(__float_as_int(x[0].x), 0);
+          const int lo_i = __builtin_amdgcn_readlane(__float_as_int(x[0].y), 0);
+          const int hi_r = __builtin_amdgcn_readlane(__float_as_int(x[0].x), 32);
+          const int hi_i = __builtin_amdgcn_readlane(__float_as_int(x[0].y), 32);
+          mr = __int_as_float(half ? hi_r : lo_r);
+          mi = __int_as_float(half ? hi_i : lo_i);
+        }
         const double dmr = mr, dmi = mi;
         mm_acc += dmr * dmr + dmi * dmi;
 #pragma unroll
@@ -1097,7 +1111,8 @@ hipError_t launch_gram(const GramLayout &L, const float2 *holo, int nt, long lon
       else hipLaunchKernelGGL((gram_partial16<true, true>), g, b, 0, s, holo, nt, npix, L.pxw, partial);
     }
     else {
-      hipLaunchKernelGGL(gram_partial64, dim3(L.groups), dim3(256), 0, s, holo, nt, npix, L.pxw, partial);
+      if (L.ref) hipLaunchKernelGGL((gram_partial64<false>), dim3(L.groups), dim3(256), 0, s, holo, nt, npix, L.pxw, partial);
+      else hipLaunchKernelGGL((gram_partial64<true>), dim3(L.groups), dim3(256), 0, s, holo, nt, npix, L.pxw, partial);
     }
   }
   const hipError_t e = hipGetLastError();

@@ -72,7 +72,8 @@ def test_autotune_picks_a_valid_choice(hh, case):
     hh.tuning_reset()
 
 
-@pytest.mark.parametrize("nt,ny,nx", [(32, 128, 128), (16, 64, 64), (31, 32, 64), (3, 8, 8), (32, 1024, 1024)])
+@pytest.mark.parametrize("nt,ny,nx", [(32, 128, 128), (16, 64, 64), (31, 32, 64), (3, 8, 8), (32, 1024, 1024),
+                                      (64, 128, 128), (33, 64, 64), (64, 1024, 2048)])
 def test_frame0_reference_covariance(hh, nt, ny, nx):
     # the covariance with the frame-0 reference of the split meets the FP32 bar on C
     import torch
