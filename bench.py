@@ -184,7 +184,8 @@ def _host_info() -> dict:
             "blas": blas}
 
 
-# The GPU machine gives one GPU a share of 16 host cores, whatever os.cpu_count() reports.
+# Host cores the all-core oracle leg uses at most: a single-GPU host's share of the CPUs
+# (16 per GPU), whatever os.cpu_count() reports.
 HOST_CORE_SHARE = 16
 
 
