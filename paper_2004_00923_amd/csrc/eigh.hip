@@ -1,8 +1,9 @@
 // Step (c), Eq. (5): C = V Lambda V^{t*} by parallel cyclic Jacobi in FP64, one workgroup.
 //
-// A sweep is m-1 rounds (m = n rounded up to even) of m/2 disjoint 2x2 Hermitian
-// rotations (round-robin pairing: every index pair once per sweep).  For a pair
-// (p, q) with a = A[p][p], b = A[q][q], beta = A[p][q], g = b - a:
+// A sweep is m-1 rounds (m = n rounded up to even; an odd n gets a zero row and
+// column, which never rotates) of m/2 disjoint 2x2 Hermitian rotations, in
+// round-robin order: every index pair meets once per sweep.  For a pair (p, q) with
+// a = A[p][p], b = A[q][q], beta = A[p][q], g = b - a:
 //   D = sqrt(g^2 + 4 |beta|^2),  den = sqrt(2 D (D + |g|)),
 //   c = (D + |g|) / den,  J[p][q] = sgn(g) 2 beta / den,  J[q][p] = -conj(J[p][q]),
 //   J[p][p] = J[q][q] = c,   A <- J^H A J,   V <- V J,
@@ -10,18 +11,29 @@
 // to A[q][q] (the textbook t = sgn(theta)/(|theta| + sqrt(1 + theta^2)),
 // theta = g / (2|beta|), rewritten to need two square roots and one division).
 //
-// Work split per round: (1) every thread rotates the 2x2 blocks {p1,q1} x {p2,q2}
-// of A it owns, in place (the four outputs share the four inputs; only the upper
-// triangle of A is kept, so each entry is read and written once); barrier;
-// (2) wave 0 computes the next round's rotations from three entries each, with
-// hardware reciprocal / reciprocal-square-root seeds refined by Newton steps,
-// while the other waves rotate V's (row, pair) entries in place, one row per lane
-// and one pair per group of lanes (the group's rotation data is one LDS
-// broadcast); barrier.  C is scaled by an exact power of two so that its Frobenius
-// norm is O(1).
-// A rotation is skipped when |beta| <= 1e-15 sqrt(|a b|) or |beta| <= 1e-18 ||C||_F;
-// the iteration stops when every off-diagonal entry passes that test.  The result
-// is sorted by decreasing eigenvalue and each eigenvector's phase is fixed.
+// Layout.  A is kept in slot coordinates: pair k of every round sits on slots 2k and
+// 2k+1, and between rounds the indices move through the slots by one fixed
+// permutation (the circle method: one index stays, the others advance one place),
+// so the A addresses a thread touches are the same in every round.  The diagonal
+// lives in the rotation data (a rotation knows its pair's new diagonal entries); the
+// off-diagonal entries live in two buffers that share one [NMAX][NMAX+1] array (the
+// upper and the lower triangle).  A round reads one buffer and writes the other,
+// already permuted for the next round, so it needs a single barrier:
+//   wave 0, lane k: the next round's rotation of pair k, from this round's data: its
+//     off-diagonal entry is one output of this round's 2x2 block rotation, recomputed
+//     here, and its diagonal entries are in this round's rotation data;
+//   the block waves: A <- J^H A J on the 2x2 blocks {2P, 2P+1} x {2Q, 2Q+1}, one
+//     column of a block per task (a pair's own block: its off-diagonal entry, which
+//     becomes zero if the pair rotates);
+//   the other waves: V <- V J in place, one (row, pair) per task; V's columns stay in
+//     index order, so a task looks up the two indices on its pair's slots.
+// Square roots and reciprocals use hardware seeds refined by Newton steps.  C is
+// scaled by an exact power of two so that its Frobenius norm is O(1).  A rotation is
+// skipped when |beta| <= 1e-15 sqrt(|a b|) or |beta| <= 1e-18 ||C||_F; the iteration
+// stops at the start of a sweep when every off-diagonal entry passes that test.  The
+// result is sorted by decreasing eigenvalue and each eigenvector's phase is fixed.
+#include <type_traits>
+
 #include "hh_internal.h"
 
 namespace hh {
@@ -29,11 +41,22 @@ namespace {
 
 constexpr double kRelTol = 1e-15;
 constexpr double kAbsTol = 1e-18;
-// threads per problem: 576 for n <= 32 (rounds are latency-bound; wave 0 computes
-// the rotations while eight waves rotate V, one (row, pair) item each), 1024 for
-// n <= 64 (a round has four times the 2x2 blocks and V items, so it is throughput-bound)
+// Workgroup per size class: wave 0 computes the rotations, kBlockWaves waves rotate
+// A's blocks, the others rotate V.  n <= 32: 13 waves, one task per lane (a round is
+// latency-bound); n <= 64: 16 waves, the most a workgroup holds (four block tasks and
+// three V tasks per lane).
 template <int NMAX>
-constexpr int threads_for() { return NMAX <= 32 ? 576 : 1024; }
+struct JacobiShape;
+template <>
+struct JacobiShape<32> {
+  static constexpr int kThreads = 832, kBlockWaves = 4;
+};
+template <>
+struct JacobiShape<64> {
+  static constexpr int kThreads = 1024, kBlockWaves = 4;
+};
+template <int NMAX>
+constexpr int threads_for() { return JacobiShape<NMAX>::kThreads; }
 constexpr size_t kCuLdsBytes = 160 * 1024;
 
 __device__ __forceinline__ double2 zmul(double2 a, double2 b) {
@@ -60,40 +83,47 @@ __device__ __forceinline__ double rcp64(double x) {
   return y;
 }
 
-// Per-round rotation data, indexed by matrix index i: cd[i] = (c_i, new diagonal
-// entry i), e[i] = J[partner][i].  A pair rotates iff its e is nonzero (a rotating
-// pair has |beta| > 1e-18 ||C||_F after scaling, so e cannot underflow to zero);
-// a pair that does not rotate has c = 1, e = 0 and its diagonal entries as they are.
+// Per-round rotation data, indexed by slot: the pair on slots p = 2k, q = 2k+1 has
+// cd[p] = (c, new A[p][p]), cd[q] = (c, new A[q][q]), e[q] = J[p][q], e[p] = J[q][p].
+// A pair rotates iff e[q] is nonzero (a rotating pair has |beta| > 1e-18 ||C||_F after
+// scaling, so J[p][q] cannot underflow to zero); a pair that does not rotate has c = 1,
+// e = 0 and its diagonal entries as they are.
 template <int NMAX>
 struct RoundParams {
   double2 cd[NMAX];
   double2 e[NMAX];
 };
 
-// Round-robin pairing: pair k of round r among m players (p < q; q may be the dummy).
-__device__ __forceinline__ void pair_of(int r, int k, int m, int &p, int &q) {
-  if (k == 0) {
-    p = r;
-    q = m - 1;
-  } else {  // (r + k) mod (m - 1) and (r - k) mod (m - 1), with 0 <= r < m - 1, 0 < k < m / 2
-    p = r + k >= m - 1 ? r + k - (m - 1) : r + k;
-    q = r - k < 0 ? r - k + (m - 1) : r - k;
-  }
-  if (p > q) {
-    const int x = p;
-    p = q;
-    q = x;
-  }
+// Circle-method schedule on m slots: slot 2k is place k and slot 2k+1 place m-1-k, so
+// the pairs (place k, place m-1-k) are the slot pairs (2k, 2k+1).  After a round the
+// index in place 0 stays and every other index advances one place (m-1 wraps to 1):
+// every two indices share a pair once in m-1 rounds, after which each index is back on
+// its own slot.
+__device__ __forceinline__ int slot_place(int s, int m) { return (s & 1) ? m - 1 - (s >> 1) : s >> 1; }
+__device__ __forceinline__ int place_slot(int p, int m) { return 2 * p < m ? 2 * p : 2 * (m - 1 - p) + 1; }
+// the slot that the entry on slot s moves to after a round, and the one it came from
+__device__ __forceinline__ int slot_after(int s, int m) {
+  const int p = slot_place(s, m);
+  return place_slot(p == 0 ? 0 : (p == m - 1 ? 1 : p + 1), m);
+}
+__device__ __forceinline__ int slot_before(int s, int m) {
+  const int p = slot_place(s, m);
+  return place_slot(p == 0 ? 0 : (p == 1 ? m - 1 : p - 1), m);
+}
+// the matrix index on slot s in round r of a sweep (0 <= r < m - 1)
+__device__ __forceinline__ int slot_index(int s, int r, int m) {
+  const int p = slot_place(s, m);
+  if (p == 0) return 0;
+  int t = p - 1 - r;
+  if (t < 0) t += m - 1;
+  return place_slot(t + 1, m);
 }
 
+// Rotation of the pair on slots 2k, 2k+1 from its diagonal entries a, b and its
+// off-diagonal entry beta.
 template <int NMAX>
-__device__ __forceinline__ void set_rotation(RoundParams<NMAX> &P, int p, int q, int n, double a, double b,
-                                             double2 beta, double abs2) {
-  if (q >= n) {  // paired with the dummy index: no rotation
-    P.cd[p] = make_double2(1.0, a);
-    P.e[p] = make_double2(0.0, 0.0);
-    return;
-  }
+__device__ __forceinline__ void set_rotation(RoundParams<NMAX> &P, int k, double a, double b, double2 beta,
+                                             double abs2) {
   // computed whether or not the pair rotates, then selected (no branch around the
   // arithmetic)
   const double ab2 = beta.x * beta.x + beta.y * beta.y;
@@ -106,23 +136,36 @@ __device__ __forceinline__ void set_rotation(RoundParams<NMAX> &P, int p, int q,
   const double c = rot ? (D + ag) * inv : 1.0;
   const double2 eq = rot ? make_double2(sg * 2.0 * inv * beta.x, sg * 2.0 * inv * beta.y)  // J[p][q]
                          : make_double2(0.0, 0.0);
-  P.cd[p] = make_double2(c, rot ? a - tab : a);
-  P.cd[q] = make_double2(c, rot ? b + tab : b);
-  P.e[q] = eq;
-  P.e[p] = rot ? make_double2(-eq.x, eq.y) : make_double2(0.0, 0.0);  // J[q][p] = -conj(J[p][q])
+  P.cd[2 * k] = make_double2(c, rot ? a - tab : a);
+  P.cd[2 * k + 1] = make_double2(c, rot ? b + tab : b);
+  P.e[2 * k + 1] = eq;
+  P.e[2 * k] = rot ? make_double2(-eq.x, eq.y) : make_double2(0.0, 0.0);  // J[q][p] = -conj(J[p][q])
 }
 
-// Entry (i, j) of the Hermitian A, of which only the upper triangle (i <= j) is
-// kept up to date.
-__device__ __forceinline__ double2 herm(const double2 *A, int LD, int i, int j) {
-  const bool up = i <= j;
-  const double2 v = A[(up ? i : j) * LD + (up ? j : i)];
-  return make_double2(v.x, up ? v.y : -v.y);
+// Off-diagonal entries in slot coordinates: buffer 0 keeps entry (x, y), x < y, at
+// [x][y], buffer 1 keeps the same value at [y][x].  Address of (x, y), x < y, in buffer b:
+template <int LD>
+__device__ __forceinline__ int abuf_addr(int b, int x, int y) { return b ? y * LD + x : x * LD + y; }
+// Writes entry (u, v), u != v in either order, into buffer b: the value of entry
+// (min, max), i.e. val conjugated when u > v.
+template <int LD>
+__device__ __forceinline__ void abuf_write(double2 *A, int b, int u, int v, double2 val) {
+  const int lo = u < v ? u : v, hi = u < v ? v : u;
+  A[abuf_addr<LD>(b, lo, hi)] = make_double2(val.x, u < v ? val.y : -val.y);
 }
-// Writes entry (i, j) at its upper-triangle position.
-__device__ __forceinline__ void herm_store(double2 *A, int LD, int i, int j, double2 v) {
-  const bool up = i <= j;
-  A[(up ? i : j) * LD + (up ? j : i)] = make_double2(v.x, up ? v.y : -v.y);
+
+// Column y of J_P^H M J_Q for a 2x2 block M of A (rows 2P, 2P+1 and columns 2Q, 2Q+1
+// in slot coordinates), given m0y = M[0][y], m0o = M[0][1-y], m1y = M[1][y],
+// m1o = M[1][1-y] and the two rotations' c and J[2P][2P+1] (cP, eP), c and J[2Q][2Q+1]
+// (cQ, eQ): entries (2P, 2Q+y) and (2P+1, 2Q+y) of the rotated block.
+__device__ __forceinline__ void block_column(double2 m0y, double2 m0o, double2 m1y, double2 m1o, double cP,
+                                             double2 eP, double cQ, double2 eQ, int y, double2 &o0,
+                                             double2 &o1) {
+  const double2 w = y ? eQ : make_double2(-eQ.x, eQ.y);  // J_Q[2Q+1-y][2Q+y]
+  const double2 t0 = zadd(zscale(m0y, cQ), zmul(m0o, w));
+  const double2 t1 = zadd(zscale(m1y, cQ), zmul(m1o, w));
+  o0 = zsub(zscale(t0, cP), zmul(eP, t1));
+  o1 = zadd(zmul(zconj(eP), t0), zscale(t1, cP));
 }
 
 // C into A (scaled by an exact power of two so that its Frobenius norm is O(1))
@@ -250,67 +293,226 @@ __device__ void store_sorted(const EighProblem &pr, const double2 *A, const doub
 template <int NMAX>
 __global__ __launch_bounds__(threads_for<NMAX>()) void eigh_jacobi(EighBatch batch, int max_sweeps) {
   constexpr int kThreads = threads_for<NMAX>();
+  constexpr int BW = JacobiShape<NMAX>::kBlockWaves;
   // one workgroup per problem of the batch
   const EighProblem &pr = batch.prob[blockIdx.x];
   const int n = pr.n;
   constexpr int LD = NMAX + 1;
   constexpr int NPMAX = NMAX / 2;
-  constexpr int NBLK = NPMAX * (NPMAX + 1) / 2;
-  constexpr int BPT = (NBLK + kThreads - 1) / kThreads;          // A blocks per thread
+  constexpr int TPB = (NPMAX * NPMAX + 64 * BW - 1) / (64 * BW);  // block tasks per lane
+  constexpr int VW = kThreads / 64 - 1 - BW;                      // waves rotating V
+  constexpr int GPW = 64 / NMAX;                                  // pairs per V wave and item
+  constexpr int NG = NPMAX / GPW;                                 // V items
+  constexpr int VPT = (NG + VW - 1) / VW;                         // V items per wave
+  static_assert(kThreads % 64 == 0 && VW > 0 && NMAX * LD < 65536, "workgroup shape");
   extern __shared__ double2 smem[];
-  double2 *const A = smem;              // [n][LD]
-  double2 *const V = smem + NMAX * LD;  // [n][LD]
+  double2 *const A = smem;              // the two off-diagonal buffers, [NMAX][LD]
+  double2 *const V = smem + NMAX * LD;  // [n][LD], columns in index order
   __shared__ RoundParams<NMAX> prm[2];
+  __shared__ double dg[NMAX];                       // diagonal in slot order, at the start of a sweep
+  __shared__ unsigned short vidx[NMAX - 1][NPMAX];  // indices on pair k's slots in round r: p | q << 8
   __shared__ int flag;
   __shared__ double red[kThreads];
   __shared__ int rank_of[NMAX];
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // the same for a wave's lanes
   const int m = n + (n & 1);
   const int np = m / 2;
-  const int nblk = np * (np + 1) / 2;
 
-  // blocks (P <= Q) owned by this thread, unranked once
-  int bP[BPT], bQ[BPT];
+  // Block tasks of waves 1..BW: task t < np is pair t's own block (its off-diagonal
+  // entry (2t, 2t+1)), task np + 2b + y column y of the b-th block P < Q.  Precomputed
+  // per task: bmeta = x0 | c0 << 8 | conj output 0 << 16 | conj output 1 << 17 | kind << 24
+  // (kind 0: none, 1: own block, 2: block column; x0 = 2P, c0 = 2Q + y); bbase = the
+  // address of M[0][y] (own block: of its entry) in buffer 0 | in buffer 1 << 16 (the
+  // block's other entries are at fixed offsets from it); bw0, bw1 = the addresses of the
+  // two outputs after the round's permutation in buffer 0 and 1 (low, high half).
+  int bmeta[TPB], bbase[TPB], bw0[TPB], bw1[TPB];
 #pragma unroll
-  for (int u = 0; u < BPT; ++u) {
-    int b = tid + kThreads * u, P = 0;
-    bP[u] = -1;
-    bQ[u] = -1;
-    if (b < nblk) {
-      while (b >= np - P) {
-        b -= np - P;
+  for (int u = 0; u < TPB; ++u) {
+    bmeta[u] = bbase[u] = bw0[u] = bw1[u] = 0;
+    const int t = (tid - 64) + 64 * BW * u;
+    if (wave < 1 || wave > BW || t >= np * np) continue;
+    if (t < np) {
+      const int x0 = 2 * t, c0 = 2 * t + 1;
+      const int w0 = slot_after(x0, m), wc = slot_after(c0, m);
+      const int lo = w0 < wc ? w0 : wc, hi = w0 < wc ? wc : w0;
+      bbase[u] = abuf_addr<LD>(0, x0, c0) | abuf_addr<LD>(1, x0, c0) << 16;
+      bw0[u] = abuf_addr<LD>(0, lo, hi);
+      bw1[u] = abuf_addr<LD>(1, lo, hi);
+      bmeta[u] = x0 | c0 << 8 | (w0 > wc) << 16 | 1 << 24;
+    } else {
+      int bi = (t - np) >> 1, P = 0;
+      const int y = (t - np) & 1;
+      while (bi >= np - 1 - P) {
+        bi -= np - 1 - P;
         ++P;
       }
-      bP[u] = P;
-      bQ[u] = P + b;
+      const int Q = P + 1 + bi;
+      const int x0 = 2 * P, c0 = 2 * Q + y;
+      const int w0 = slot_after(x0, m), w1 = slot_after(x0 + 1, m), wc = slot_after(c0, m);
+      bbase[u] = abuf_addr<LD>(0, x0, c0) | abuf_addr<LD>(1, x0, c0) << 16;
+      bw0[u] = abuf_addr<LD>(0, w0 < wc ? w0 : wc, w0 < wc ? wc : w0) |
+               abuf_addr<LD>(0, w1 < wc ? w1 : wc, w1 < wc ? wc : w1) << 16;
+      bw1[u] = abuf_addr<LD>(1, w0 < wc ? w0 : wc, w0 < wc ? wc : w0) |
+               abuf_addr<LD>(1, w1 < wc ? w1 : wc, w1 < wc ? wc : w1) << 16;
+      bmeta[u] = x0 | c0 << 8 | (w0 > wc) << 16 | (w1 > wc) << 17 | 2 << 24;
     }
   }
 
-  // V items: waves 1.. rotate V with one row per lane, the wave's lanes in groups of
-  // NMAX rows that each take one pair, so the rotation data a group reads is one
-  // LDS broadcast.  Item g of a wave is the pairs GPW g .. GPW g + GPW - 1.
-  constexpr int GPW = 64 / NMAX;                  // pairs per wave and item
-  constexpr int VW = kThreads / 64 - 1;           // waves rotating V
-  constexpr int NG = NPMAX / GPW;                 // items
-  constexpr int VPT = (NG + VW - 1) / VW;         // items per wave
-  const int vrow = (tid & 63) % NMAX, vsub = (tid & 63) / NMAX, vwave = (tid >> 6) - 1;
+  // Rotation lanes (wave 0, lane k < np): the next round's pair k is on slots rs0, rs1
+  // in this round; its off-diagonal entry is row rx of column ry of this round's block
+  // (rx0 / 2, rcq / 2), rx0 < rcq, conjugated when rs0's pair is the later one (rconj);
+  // rbase as bbase.  For m = 2 the pair is the same in every round (rsame; rbase: the
+  // entry (0, 1)).
+  int rs0 = 0, rs1 = 0, rx0 = 0, rcq = 0, rbase = 0, rflags = 0;  // rflags: ry | rx << 1 | rconj << 2 | rsame << 3
+  if (wave == 0 && lane < np) {
+    rs0 = slot_before(2 * lane, m);
+    rs1 = slot_before(2 * lane + 1, m);
+    const int P0 = rs0 >> 1, P1 = rs1 >> 1;
+    const bool rsame = P0 == P1, rconj = P0 > P1;
+    const int rP = rconj ? P1 : P0, rQ = rconj ? P0 : P1;
+    const int rx = (rconj ? rs1 : rs0) & 1, ry = (rconj ? rs0 : rs1) & 1;
+    rx0 = 2 * rP;
+    rcq = 2 * rQ;
+    const int xa = rsame ? 0 : rx0, ca = rsame ? 1 : rcq + ry;
+    rbase = abuf_addr<LD>(0, xa, ca) | abuf_addr<LD>(1, xa, ca) << 16;
+    rflags = ry | rx << 1 | rconj << 2 | rsame << 3;
+  }
+
+  // V tasks of the other waves: one row per lane, the wave's lanes in groups of NMAX
+  // rows that each take one pair, so the rotation data and the indices a group reads
+  // are LDS broadcasts.  Item g of a wave is the pairs GPW g .. GPW g + GPW - 1.
+  const int vl = tid - 64 * (1 + BW);
+  const int vrow = (vl & 63) % NMAX, vsub = (vl & 63) / NMAX, vwave = vl >> 6;
 
   const double scale = load_scaled<NMAX, kThreads>(pr, A, V, red);
   const double fro = red[0] / scale;  // Frobenius norm of C (exactly, scale is a power of two)
   const double abs2 = (kAbsTol * fro * scale) * (kAbsTol * fro * scale);
+  // the diagonal out of A; the zero row and column of an odd n (buffer 0 and V); the
+  // index table of the V tasks
+  if (tid < NMAX) dg[tid] = tid < n ? A[tid * LD + tid].x : 0.0;
+  if (m > n) {
+    for (int i = tid; i < n; i += kThreads) {
+      A[i * LD + n] = make_double2(0.0, 0.0);
+      V[i * LD + n] = make_double2(0.0, 0.0);
+    }
+  }
+  for (int e = tid; e < (m - 1) * np; e += kThreads) {
+    const int r = e / np, k = e - (e / np) * np;
+    vidx[r][k] = (unsigned short)(slot_index(2 * k, r, m) | slot_index(2 * k + 1, r, m) << 8);
+  }
+  __syncthreads();
+  // the first round's rotations (the slots hold the indices in order)
+  if (tid < np) set_rotation(prm[0], tid, dg[2 * tid], dg[2 * tid + 1], A[2 * tid * LD + 2 * tid + 1], abs2);
   __syncthreads();
 
-  int sweeps = 0;
+  // One round, reading buffer and rotation data PB, writing buffer and rotation data PB ^ 1.
+  auto round = [&](auto pb_const, int r) {
+    constexpr int PB = decltype(pb_const)::value;
+    const RoundParams<NMAX> &P = prm[PB];
+    // the other three entries of a block column, from the address of M[0][y] in buffer
+    // PB: M[0][1-y] one column over, M[1][.] one row down
+    constexpr int kColStep = PB ? LD : 1, kRowStep = PB ? 1 : LD;
+    if (wave == 0) {
+      // the next round's rotations (after the last round of a sweep: the first round
+      // of the next one)
+      if (lane < np) {
+        const int base = PB ? rbase >> 16 : rbase & 0xffff;
+        double bx, by;
+        if (rflags & 8) {
+          const double2 e1 = P.e[1];
+          const double2 v = A[base];
+          const bool rot = e1.x != 0.0 || e1.y != 0.0;
+          bx = rot ? 0.0 : v.x;
+          by = rot ? 0.0 : v.y;
+        } else {
+          const int ry = rflags & 1, d = ry ? -kColStep : kColStep;
+          const double2 m0y = A[base], m0o = A[base + d];
+          const double2 m1y = A[base + kRowStep], m1o = A[base + d + kRowStep];
+          double2 o0, o1;
+          block_column(m0y, m0o, m1y, m1o, P.cd[rx0].x, P.e[rx0 + 1], P.cd[rcq].x, P.e[rcq + 1], ry, o0, o1);
+          const bool rx = rflags & 2;
+          bx = rx ? o1.x : o0.x;
+          by = rx ? o1.y : o0.y;
+          by = (rflags & 4) ? -by : by;
+        }
+        const double a2 = P.cd[rs0].y, b2 = P.cd[rs1].y;
+        set_rotation(prm[PB ^ 1], lane, a2, b2, make_double2(bx, by), abs2);
+        dg[2 * lane] = a2;
+        dg[2 * lane + 1] = b2;
+      }
+    } else if (wave <= BW) {
+      // A <- J^H A J from buffer PB, written permuted into buffer PB ^ 1
+#pragma unroll
+      for (int u = 0; u < TPB; ++u) {
+        // opaque to the compiler, so that the decoding below stays in the round (hoisted,
+        // it would keep every task's addresses of both buffers in registers)
+        int meta = bmeta[u], bb = bbase[u], ww0 = bw0[u], ww1 = bw1[u];
+        asm volatile("" : "+v"(meta), "+v"(bb), "+v"(ww0), "+v"(ww1));
+        const int kind = meta >> 24;
+        if (kind == 0) continue;
+        const int x0 = meta & 255, c0 = (meta >> 8) & 255;
+        const int base = PB ? bb >> 16 : bb & 0xffff;
+        const int wa = PB ? ww0 : ww1;
+        if (kind == 1) {
+          const double2 beta = A[base];
+          const double2 e1 = P.e[c0];
+          const bool rot = e1.x != 0.0 || e1.y != 0.0;
+          A[wa & 0xffff] = rot ? make_double2(0.0, 0.0) : make_double2(beta.x, (meta >> 16) & 1 ? -beta.y : beta.y);
+        } else {
+          const int d = (c0 & 1) ? -kColStep : kColStep;
+          const double2 m0y = A[base], m0o = A[base + d];
+          const double2 m1y = A[base + kRowStep], m1o = A[base + d + kRowStep];
+          double2 o0, o1;
+          block_column(m0y, m0o, m1y, m1o, P.cd[x0].x, P.e[x0 + 1], P.cd[c0 & ~1].x, P.e[c0 | 1], c0 & 1, o0, o1);
+          A[wa & 0xffff] = make_double2(o0.x, (meta >> 16) & 1 ? -o0.y : o0.y);
+          A[wa >> 16] = make_double2(o1.x, (meta >> 17) & 1 ? -o1.y : o1.y);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+      }
+    } else {
+      // V <- V J in place: every operand is loaded first, then the items are rotated (a
+      // pair that does not rotate has c = 1, e = 0 and is rotated all the same)
+      double2 vp[VPT], vq[VPT], eq[VPT], ep[VPT];
+      double cc[VPT];
+      int ip[VPT], iq[VPT];
+#pragma unroll
+      for (int u = 0; u < VPT; ++u) {
+        const int g = vwave + VW * u;
+        const int k = g * GPW + vsub;
+        const bool ok = g < NG && k < np && vrow < n;
+        const int kk = ok ? k : 0, row = ok ? vrow : 0;
+        const int pq = vidx[r][kk];
+        ip[u] = ok ? row * LD + (pq & 255) : -1;
+        iq[u] = row * LD + (pq >> 8);
+        vp[u] = V[row * LD + (pq & 255)];
+        vq[u] = V[iq[u]];
+        cc[u] = P.cd[2 * kk].x;
+        eq[u] = P.e[2 * kk + 1];  // J[p][q]
+        ep[u] = P.e[2 * kk];      // J[q][p]
+      }
+#pragma unroll
+      for (int u = 0; u < VPT; ++u) {
+        if (ip[u] >= 0) {
+          V[ip[u]] = zadd(zscale(vp[u], cc[u]), zmul(vq[u], ep[u]));
+          V[iq[u]] = zadd(zmul(vp[u], eq[u]), zscale(vq[u], cc[u]));
+        }
+      }
+    }
+  };
+
+  int sweeps = 0, pb = 0;  // pb: the buffer and the rotation data of the current round
   bool converged = false;
   for (;;) {
+    // at the start of a sweep every index is on its own slot
     if (tid == 0) flag = 0;
     __syncthreads();
     for (int e = tid; e < n * n; e += kThreads) {
       const int i = e / n, j = e - (e / n) * n;
       if (i < j) {
-        const double2 b = A[i * LD + j];
+        const double2 b = A[abuf_addr<LD>(pb, i, j)];
         const double ab2 = b.x * b.x + b.y * b.y;
-        if (ab2 > kRelTol * kRelTol * fabs(A[i * LD + i].x * A[j * LD + j].x) && ab2 > abs2) flag = 1;
+        if (ab2 > kRelTol * kRelTol * fabs(dg[i] * dg[j]) && ab2 > abs2) flag = 1;
       }
     }
     __syncthreads();
@@ -320,110 +522,18 @@ __global__ __launch_bounds__(threads_for<NMAX>()) void eigh_jacobi(EighBatch bat
     }
     if (sweeps >= max_sweeps) break;
     ++sweeps;
-
-    if (tid < np) {
-      int p, q;
-      pair_of(0, tid, m, p, q);
-      const int qc = q < n ? q : p;
-      set_rotation(prm[0], p, q, n, A[p * LD + p].x, A[qc * LD + qc].x, A[p * LD + qc], abs2);
-    }
-    __syncthreads();
-
-    int pb = 0;
     for (int r = 0; r < m - 1; ++r) {
-      const RoundParams<NMAX> &P = prm[pb];
-      // (1) A <- J^H A J on the blocks this thread owns (in place: an entry of the upper
-      // triangle belongs to one block)
-#pragma unroll
-      for (int u = 0; u < BPT; ++u) {
-        if (bP[u] < 0) continue;
-        // the pairing is fixed arithmetic: recomputed in registers (no dependent LDS read)
-        int p1, q1, p2, q2;
-        pair_of(r, bP[u], m, p1, q1);
-        pair_of(r, bQ[u], m, p2, q2);
-        // One instruction stream for the pair's own block (P == Q) and the others:
-        // every operand is loaded first; on the own block of a rotating pair the
-        // rotated values are replaced by the exact ones (zero off-diagonal, moved
-        // diagonal).  A pair that does not rotate has c = 1, e = 0, for which the
-        // products below return its entries unchanged.
-        const bool own = bP[u] == bQ[u];
-        const bool vq1 = q1 < n, vq2 = q2 < n;
-        // value selects (clamped indices), never a select between LDS and a local
-        const int q1c = vq1 ? q1 : p1, q2c = vq2 ? q2 : p2;
-        const double m1 = vq1 ? 1.0 : 0.0, m2 = vq2 ? 1.0 : 0.0;
-        const double2 a = herm(A, LD, p1, p2);
-        const double2 b = zscale(herm(A, LD, p1, q2c), m2);
-        const double2 d = zscale(herm(A, LD, q1c, p2), m1);
-        const double2 f = zscale(herm(A, LD, q1c, q2c), m1 * m2);
-        const double2 cd1 = P.cd[p1];
-        const double c1 = cd1.x, dp = cd1.y, dq = P.cd[q1c].y, c2 = P.cd[p2].x;
-        const double2 e1 = zscale(P.e[q1c], m1);  // J[p1][q1]
-        const double2 e2 = zscale(P.e[q2c], m2);  // J[p2][q2]
-        const bool rot = e1.x != 0.0 || e1.y != 0.0;
-        // T = M J2 (columns p2, q2), then J1^H T (rows p1, q1)
-        const double2 me2c = make_double2(-e2.x, e2.y);  // J[q2][p2]
-        const double2 t00 = zadd(zscale(a, c2), zmul(b, me2c)), t01 = zadd(zmul(a, e2), zscale(b, c2));
-        const double2 t10 = zadd(zscale(d, c2), zmul(f, me2c)), t11 = zadd(zmul(d, e2), zscale(f, c2));
-        double2 o00 = zsub(zscale(t00, c1), zmul(e1, t10));
-        double2 o01 = zsub(zscale(t01, c1), zmul(e1, t11));
-        const double2 e1c = zconj(e1);
-        const double2 o10 = zadd(zmul(e1c, t00), zscale(t10, c1));
-        double2 o11 = zadd(zmul(e1c, t01), zscale(t11, c1));
-        if (own && rot) {
-          o00 = make_double2(dp, 0.0);
-          o11 = make_double2(dq, 0.0);
-          o01 = make_double2(0.0, 0.0);
-        }
-        herm_store(A, LD, p1, p2, o00);
-        if (vq2) herm_store(A, LD, p1, q2, o01);
-        if (vq1 && !own) herm_store(A, LD, q1, p2, o10);  // on the own block: o01's entry
-        if (vq1 && vq2) herm_store(A, LD, q1, q2, o11);
-      }
-      __syncthreads();
-      if (tid < 64) {
-        // (2a) wave 0: the next round's rotations from the updated A
-        if (r + 1 < m - 1 && tid < np) {
-          int p, q;
-          pair_of(r + 1, tid, m, p, q);
-          const int qc = q < n ? q : p;
-          set_rotation(prm[pb ^ 1], p, q, n, A[p * LD + p].x, A[qc * LD + qc].x, A[p * LD + qc], abs2);
-        }
-      } else {
-        // (2b) waves 1..: V <- V J, one (row, pair) entry pair per lane and item; every
-        // operand is loaded first, then the items are rotated (a pair that does not
-        // rotate has c = 1, e = 0 and is rotated all the same)
-        double2 vp[VPT], vq[VPT], eq[VPT], ep[VPT];
-        double cc[VPT];
-        int ip[VPT], iq[VPT];
-#pragma unroll
-        for (int u = 0; u < VPT; ++u) {
-          const int k = (vwave + VW * u) * GPW + vsub;
-          const bool ok = vwave + VW * u < NG && k < np && vrow < n;
-          int p = 0, q = 0;
-          if (ok) pair_of(r, k, m, p, q);
-          const int row = ok ? vrow : 0;
-          const int qc = q < n ? q : p;
-          ip[u] = row * LD + p;
-          iq[u] = ok && q < n ? row * LD + q : -1;
-          vp[u] = V[row * LD + p];
-          vq[u] = V[row * LD + qc];
-          cc[u] = P.cd[p].x;
-          eq[u] = P.e[qc];  // J[p][q]
-          ep[u] = P.e[p];   // J[q][p]
-        }
-#pragma unroll
-        for (int u = 0; u < VPT; ++u) {
-          if (iq[u] >= 0) {
-            V[ip[u]] = zadd(zscale(vp[u], cc[u]), zmul(vq[u], ep[u]));
-            V[iq[u]] = zadd(zmul(vp[u], eq[u]), zscale(vq[u], cc[u]));
-          }
-        }
-      }
+      if (pb)
+        round(std::integral_constant<int, 1>{}, r);
+      else
+        round(std::integral_constant<int, 0>{}, r);
       __syncthreads();
       pb ^= 1;
     }
   }
 
+  for (int i = tid; i < n; i += kThreads) A[i * LD + i] = make_double2(dg[i], 0.0);
+  __syncthreads();
   store_sorted<NMAX>(pr, A, V, scale, rank_of, converged ? sweeps : -1);
 }
 
@@ -653,7 +763,8 @@ __global__ __launch_bounds__(256) void eigh_tridiag(EighBatch batch, int max_ite
 
 template <int NMAX>
 constexpr size_t eigh_static_lds() {
-  return 2 * sizeof(RoundParams<NMAX>) + sizeof(int) + threads_for<NMAX>() * sizeof(double) + NMAX * sizeof(int) + 512;
+  return 2 * sizeof(RoundParams<NMAX>) + sizeof(int) + threads_for<NMAX>() * sizeof(double) + NMAX * sizeof(int) +
+         NMAX * sizeof(double) + (NMAX - 1) * (NMAX / 2) * sizeof(unsigned short) + 512;
 }
 
 template <int NMAX>
