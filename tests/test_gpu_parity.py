@@ -81,7 +81,7 @@ def test_covariance_parity(hh, nt, ny, nx):
 
 
 @pytest.mark.parametrize("solver", ["jacobi", "tridiag"])
-@pytest.mark.parametrize("n", [2, 3, 5, 8, 16, 31, 32, 33, 48, 64])
+@pytest.mark.parametrize("n", [2, 3, 4, 5, 8, 16, 17, 31, 32, 33, 48, 63, 64])
 def test_eigh_parity_random(hh, n, solver):
     import torch
     say(f"eigh n={n} {solver}")
