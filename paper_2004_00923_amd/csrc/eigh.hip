@@ -29,8 +29,10 @@
 //     index order, so a task looks up the two indices on its pair's slots.
 // Square roots and reciprocals use hardware seeds refined by Newton steps.  C is
 // scaled by an exact power of two so that its Frobenius norm is O(1).  A rotation is
-// skipped when |beta| <= 1e-15 sqrt(|a b|) or |beta| <= 1e-18 ||C||_F; the iteration
-// stops at the start of a sweep when every off-diagonal entry passes that test.  The
+// skipped when |beta| <= 1e-15 sqrt(|a b|) or |beta| <= 1e-16 ||C||_F (about the unit
+// roundoff times ||C||: such an entry is within the rounding already made in forming C
+// and in every rotation); the iteration stops at the start of a sweep when every
+// off-diagonal entry passes that test.  The
 // result is sorted by decreasing eigenvalue and each eigenvector's phase is fixed.
 #include <type_traits>
 
@@ -40,7 +42,7 @@ namespace hh {
 namespace {
 
 constexpr double kRelTol = 1e-15;
-constexpr double kAbsTol = 1e-18;
+constexpr double kAbsTol = 1e-16;
 // Workgroup per size class: wave 0 computes the rotations, kBlockWaves waves rotate
 // A's blocks, the others rotate V.  n <= 32: 13 waves, one task per lane (a round is
 // latency-bound); n <= 64: 16 waves, the most a workgroup holds (four block tasks and
@@ -85,7 +87,7 @@ __device__ __forceinline__ double rcp64(double x) {
 
 // Per-round rotation data, indexed by slot: the pair on slots p = 2k, q = 2k+1 has
 // cd[p] = (c, new A[p][p]), cd[q] = (c, new A[q][q]), e[q] = J[p][q], e[p] = J[q][p].
-// A pair rotates iff e[q] is nonzero (a rotating pair has |beta| > 1e-18 ||C||_F after
+// A pair rotates iff e[q] is nonzero (a rotating pair has |beta| > 1e-16 ||C||_F after
 // scaling, so J[p][q] cannot underflow to zero); a pair that does not rotate has c = 1,
 // e = 0 and its diagonal entries as they are.
 template <int NMAX>
