@@ -428,7 +428,11 @@ hh_status hh_autotune(const hh_params *p, const uint16_t *frames, void *workspac
  *   image[p] = sum_{f=k_lo..k_hi} |sum_t H[p][t] W[t][f]|^2,
  *   W[t][f] = exp(-2 i pi t f / nt) / sqrt(nt), 0-based frequency indices
  *   (the paper's 1-based n1..n2 maps to n1-1..n2-1).
- * Uses nx, ny, nt, k_lo, k_hi, proj_mode of *p.
+ * holo: complex64 [nt][ny][nx] on the device (16-byte aligned); image: float32
+ * [ny][nx] on the device.  A power-of-two nt <= 64 is transformed along t per
+ * pixel (an FFT in registers; proj_mode is not used); any other nt is projected
+ * onto the band's basis columns in the mode proj_mode.  Uses nx, ny, nt, k_lo,
+ * k_hi, proj_mode of *p.
  */
 hh_status hh_fourier_render(const hh_params *p, const float *holo, float *image, void *stream);
 

@@ -14,6 +14,7 @@
 #include <vector>
 
 #include "hh_internal.h"
+#include "fourier.h"
 
 namespace hh {
 
@@ -811,10 +812,19 @@ hh_status hh_fourier_render(const hh_params *p, const float *holo, float *image,
   if ((st = check_stack(p)) || (st = check_select(p)) || (st = check_holo_proj(p))) return st;
   if (!holo || !image) return fail(HH_E_INVALID, "holo, image must be non-NULL");
   if (!aligned(holo, 16) || !aligned(image, 8)) return fail(HH_E_INVALID, "holo/image misaligned");
-  const double *W = get_dft_basis(p->nt);
-  if (!W) return fail(HH_E_DEVICE, "DFT basis upload failed");
-  hipError_t e = launch_project(reinterpret_cast<const float2 *>(holo), p->nt, (long long)p->nx * p->ny, W, p->k_lo,
-                                p->k_hi, p->proj_mode, image, (hipStream_t)stream);
+  const long long npix = (long long)p->nx * p->ny;
+  hipError_t e;
+  if (fourier_band_supported(p->nt)) {
+    // a power-of-two n_t: every pixel's DFT along t in registers
+    e = launch_fourier_band(reinterpret_cast<const float2 *>(holo), p->nt, npix, p->k_lo, p->k_hi, image,
+                            (hipStream_t)stream);
+  } else {
+    // any other n_t: the projection onto the band's DFT basis columns
+    const double *W = get_dft_basis(p->nt);
+    if (!W) return fail(HH_E_DEVICE, "DFT basis upload failed");
+    e = launch_project(reinterpret_cast<const float2 *>(holo), p->nt, npix, W, p->k_lo, p->k_hi, p->proj_mode, image,
+                       (hipStream_t)stream);
+  }
   if (e != hipSuccess) return device_fail(e, "hh_fourier_render");
   return HH_OK;
 }

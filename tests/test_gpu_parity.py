@@ -200,12 +200,18 @@ def test_project_parity(hh, mode, nt, ny, nx, k_lo, k_hi):
     assert np.abs(M[big] - R[big]).max() / R[big].max() <= 1e-4
 
 
-def test_fourier_parity(hh):
+# power-of-two nt take the per-pixel FFT along t, others the projection onto the basis;
+# 8 x 16 frames (128 pixels) leave a partial 256-pixel block
+@pytest.mark.parametrize("nt,ny,nx", [(32, 64, 64), (16, 64, 64), (64, 64, 64), (2, 64, 64), (24, 64, 64),
+                                      (32, 8, 16)])
+def test_fourier_parity(hh, nt, ny, nx):
     import torch
-    nt, ny, nx = 32, 64, 64
+    say(f"fourier nt={nt} {ny}x{nx}")
     f = gen_stack(4, nt, ny, nx)
     H = oracle.fresnel_ref(f, LAM, Z, PITCH).astype(np.complex64)
-    for lo, hi in [(7, 23), (0, 31), (1, 1)]:
+    bands = [(7, 23)] if nt == 32 else []
+    bands += [(0, nt - 1), (1, 1), (nt // 4, (3 * nt) // 4), (nt - 1, nt - 1)]
+    for lo, hi in bands:
         p = hh.Params(nx=nx, ny=ny, nt=nt, k_lo=lo, k_hi=hi)
         img = torch.empty((ny, nx), dtype=torch.float32, device="cuda")
         hh.hh_fourier_render(p, to_dev(H), img)
