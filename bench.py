@@ -251,9 +251,10 @@ def main():
     ap.add_argument("--tuning", default=None,
                     help="launch choices 'rows,cols,pxw,group[,gram_ref[,fused]]', e.g. 2,0,512,0 (default: the pinned "
                          "ones)")
-    ap.add_argument("--workload", default="stack", choices=["stack", "batched8", "serve"],
+    ap.add_argument("--workload", default="stack", choices=["stack", "batched8", "serve", "eigh"],
                     help="stack: the 1024^2 x 32 headline; batched8: 8 uneven stacks replayed as one HIP graph; "
-                         "serve: two simulated cameras through the streaming server")
+                         "serve: two simulated cameras through the streaming server; eigh: the eigensolver alone "
+                         "at 16, 32 and 64 frames")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -282,6 +283,8 @@ def main():
         return bench_batched8(args, hh, torch, dev)
     if args.workload == "serve":
         return bench_serve(args, hh, torch, dev)
+    if args.workload == "eigh":
+        return bench_eigh(args, hh, torch, dev)
     print("bench: generating 4 synthetic 32x1024x1024 stacks", file=sys.stderr, flush=True)
     host = [gen_stack(s, NT, NY, NX) for s in range(4)]
     frames = [torch.from_numpy(f).to(dev) for f in host]
@@ -455,6 +458,49 @@ def main():
         print("bench: timing the FP64 oracle on the host", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(host)
     print(json.dumps(out), flush=True)
+
+def bench_eigh(args, hh, torch, dev):
+    """The FP64 eigensolver alone (Eq. (5)): the covariance of one seeded 128^2 stack of
+    16, 32 and 64 frames, formed on the GPU (hh_fresnel, hh_covariance), solved one
+    problem per launch by the Jacobi solver and by the Householder + QL solver; HIP
+    events on the launch stream, median and minimum over the timed launches."""
+    import numpy as np
+    from paper_2004_00923_amd.synth import gen_stack
+    reps = max(5, min(args.steps, 200))
+    out = {}
+    for n in (16, 32, 64):
+        p = hh.Params(nx=128, ny=128, nt=n, k_lo=0, k_hi=n - 1)
+        frames = torch.from_numpy(gen_stack(3, n, 128, 128)).to(dev)
+        holo = torch.empty((n, 128, 128), dtype=torch.complex64, device=dev)
+        hh.hh_fresnel(p, frames, holo)
+        ws = hh.alloc_workspace(hh.covariance_workspace_bytes(p), dev)
+        cov = torch.empty((n, n), dtype=torch.complex128, device=dev)
+        hh.hh_covariance(p, holo, cov, ws)
+        ev = torch.empty(n, dtype=torch.float64, device=dev)
+        V = torch.empty((n, n), dtype=torch.complex128, device=dev)
+        info = torch.empty(1, dtype=torch.int32, device=dev)
+        solvers = (("jacobi", lambda: hh.hh_eigh(n, cov, ev, V, info)),
+                   ("tridiag", lambda: hh.hh_eigh_tridiag(n, cov, ev, V, info)))
+        for name, fn in solvers:
+            for _ in range(max(1, args.warmup // 10)):
+                fn()
+            torch.cuda.synchronize()
+            ts = []
+            for _ in range(reps):
+                a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                a.record()
+                fn()
+                b.record()
+                b.synchronize()
+                ts.append(a.elapsed_time(b) * 1e3)
+            out[f"{name}_{n}"] = {"median_us": float(np.median(ts)), "min_us": float(min(ts)),
+                                  "info": int(info.item())}
+    print(json.dumps({"metric": "FP64 eigensolver time per problem (one workgroup per problem)", "unit": "us",
+                      "higher_is_better": False, "data": "synthetic", "steps": reps,
+                      "config": {"workload": "eigh of the covariance of one seeded 128x128 stack of 16, 32 and 64 "
+                                             "frames, one problem per launch"},
+                      "results": out}), flush=True)
+
 
 def bench_batched8(args, hh, torch, dev):
     """8 uneven stacks (frames 512^2, 1024^2, 2048x1024; 16, 32, 64 frames; seeds
