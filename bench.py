@@ -635,10 +635,17 @@ def bench_serve(args, hh, torch, dev):
         sm["output_gvoxel_per_s"] = sm["windows_per_s"] * 32 * 1024 * 1024 / 1e9
         # algorithmic bytes per output: one new frame read as uint16 and written as a
         # hologram, the window's 32 holograms read once, the image
-        fb = 1024 * 1024 * (2 + 8 + 32 * 8 + 4)
+        # algorithmic bytes per window: the new frame in, its hologram written and read once,
+        # the image out; a window that reads its 32 holograms itself moves 270 B per pixel
+        # (runs of consecutive windows rendered in one launch share 31 of them through the cache)
+        fb = 1024 * 1024 * (2 + 8 + 8 + 4)
+        fr = 1024 * 1024 * (2 + 8 + 32 * 8 + 4)
         gbs = sm["windows_per_s"] * fb / 1e9
         sm["roofline"] = {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                          "frac": gbs / HBM_PEAK_GBS, "bytes_per_window": fb}
+                          "frac": gbs / HBM_PEAK_GBS, "bytes_per_window": fb,
+                          "window_reads_gbs": sm["windows_per_s"] * fr / 1e9,
+                          "window_reads_frac": sm["windows_per_s"] * fr / 1e9 / HBM_PEAK_GBS,
+                          "window_reads_bytes_per_window": fr}
         fourier["paced" if paced else "unthrottled"] = sm
     out = {"metric": "frame-to-image latency p99 (ms), camera A 1024^2 at 500 frames/s, with camera B",
            "value": a["p99_ms"], "unit": "ms", "n_gpus": 1, "steps": 40, "warmup": 4,

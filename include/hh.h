@@ -436,6 +436,18 @@ hh_status hh_autotune(const hh_params *p, const uint16_t *frames, void *workspac
  */
 hh_status hh_fourier_render(const hh_params *p, const float *holo, float *image, void *stream);
 
+/*
+ * Fourier demodulation of nwin windows of a frame stream, Eqs. (8)-(9): window w
+ * takes the nt holograms holo[w*hop .. w*hop + nt - 1] and its image, images[w],
+ * is the band power of hh_fourier_render (equal to it window by window).
+ * holo: complex64 [(nwin - 1)*hop + nt][ny][nx] on the device (16-byte aligned);
+ * images: float32 [nwin][ny][nx] on the device.  1 <= nwin <= 4096,
+ * 1 <= hop <= 4096.  One launch for every window: the frames that consecutive
+ * windows share are read from the cache.
+ */
+hh_status hh_fourier_render_windows(const hh_params *p, const float *holo, int32_t nwin, int32_t hop, float *images,
+                                    void *stream);
+
 /* Static text for a status code. */
 const char *hh_status_string(hh_status s);
 

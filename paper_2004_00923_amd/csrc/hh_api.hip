@@ -807,26 +807,42 @@ hh_status hh_project_frames(const hh_params *p, const uint16_t *frames, const do
   return HH_OK;
 }
 
-hh_status hh_fourier_render(const hh_params *p, const float *holo, float *image, void *stream) {
+namespace {
+// Fourier demodulation of nwin windows w of the frames holo[w hop .. w hop + nt - 1].
+hh_status fourier_windows(const hh_params *p, const float *holo, int nwin, int hop, float *images, void *stream,
+                          const char *who) {
   hh_status st;
   if ((st = check_stack(p)) || (st = check_select(p)) || (st = check_holo_proj(p))) return st;
-  if (!holo || !image) return fail(HH_E_INVALID, "holo, image must be non-NULL");
-  if (!aligned(holo, 16) || !aligned(image, 8)) return fail(HH_E_INVALID, "holo/image misaligned");
+  if (!holo || !images) return fail(HH_E_INVALID, "holo, images must be non-NULL");
+  if (!aligned(holo, 16) || !aligned(images, 8)) return fail(HH_E_INVALID, "holo/images misaligned");
+  if (nwin < 1 || nwin > 4096 || hop < 1 || hop > 4096)
+    return fail(HH_E_INVALID, "nwin=%d hop=%d: must be in [1, 4096]", nwin, hop);
   const long long npix = (long long)p->nx * p->ny;
-  hipError_t e;
+  hipError_t e = hipSuccess;
   if (fourier_band_supported(p->nt)) {
     // a power-of-two n_t: every pixel's DFT along t in registers
-    e = launch_fourier_band(reinterpret_cast<const float2 *>(holo), p->nt, npix, p->k_lo, p->k_hi, image,
+    e = launch_fourier_band(reinterpret_cast<const float2 *>(holo), p->nt, npix, nwin, hop, p->k_lo, p->k_hi, images,
                             (hipStream_t)stream);
   } else {
-    // any other n_t: the projection onto the band's DFT basis columns
+    // any other n_t: the projection onto the band's DFT basis columns, window by window
     const double *W = get_dft_basis(p->nt);
     if (!W) return fail(HH_E_DEVICE, "DFT basis upload failed");
-    e = launch_project(reinterpret_cast<const float2 *>(holo), p->nt, npix, W, p->k_lo, p->k_hi, p->proj_mode, image,
-                       (hipStream_t)stream);
+    for (int w = 0; w < nwin && e == hipSuccess; ++w)
+      e = launch_project(reinterpret_cast<const float2 *>(holo) + (long long)w * hop * npix, p->nt, npix, W, p->k_lo,
+                         p->k_hi, p->proj_mode, images + (long long)w * npix, (hipStream_t)stream);
   }
-  if (e != hipSuccess) return device_fail(e, "hh_fourier_render");
+  if (e != hipSuccess) return device_fail(e, who);
   return HH_OK;
+}
+}  // namespace
+
+hh_status hh_fourier_render(const hh_params *p, const float *holo, float *image, void *stream) {
+  return fourier_windows(p, holo, 1, 1, image, stream, "hh_fourier_render");
+}
+
+hh_status hh_fourier_render_windows(const hh_params *p, const float *holo, int32_t nwin, int32_t hop, float *images,
+                                    void *stream) {
+  return fourier_windows(p, holo, nwin, hop, images, stream, "hh_fourier_render_windows");
 }
 
 hh_status hh_pipeline(const hh_params *p, const uint16_t *frames, float *image, double *evals, double *evecs,

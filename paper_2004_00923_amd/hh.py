@@ -105,6 +105,8 @@ SIGNATURES = {
     "hh_project_frames": (ctypes.c_int32, [ctypes.POINTER(hh_params), _P, _P, _P, _P, ctypes.c_size_t, _P]),
     "hh_pipeline": (ctypes.c_int32, [ctypes.POINTER(hh_params), _P, _P, _P, _P, _P, _P, ctypes.c_size_t, _P]),
     "hh_fourier_render": (ctypes.c_int32, [ctypes.POINTER(hh_params), _P, _P, _P]),
+    "hh_fourier_render_windows": (ctypes.c_int32, [ctypes.POINTER(hh_params), _P, ctypes.c_int32, ctypes.c_int32, _P,
+                                                   _P]),
     "hh_svd_filter": (ctypes.c_int32, [ctypes.POINTER(hh_params), _P, _P, _P, _P]),
     "hh_batch_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(hh_params), ctypes.c_int32]),
     "hh_pipeline_batch": (ctypes.c_int32, [ctypes.POINTER(hh_params), ctypes.c_int32, ctypes.POINTER(hh_stack), _P,
@@ -295,6 +297,16 @@ def hh_fourier_render(p: Params, holo, image, stream=None):
     _dev_tensor(image, torch.float32, (p.ny, p.nx), "image")
     _check(lib().hh_fourier_render(ctypes.byref(p.c()), _ptr(holo), _ptr(image), _stream(stream)))
     return image
+
+
+def hh_fourier_render_windows(p: Params, holo, nwin: int, hop: int, images, stream=None):
+    """Eqs. (8)-(9) for nwin windows of a stream: window w is holo[w*hop : w*hop + nt]."""
+    import torch
+    _dev_tensor(holo, torch.complex64, ((nwin - 1) * hop + p.nt, p.ny, p.nx), "holo")
+    _dev_tensor(images, torch.float32, (nwin, p.ny, p.nx), "images")
+    _check(lib().hh_fourier_render_windows(ctypes.byref(p.c()), _ptr(holo), nwin, hop, _ptr(images),
+                                           _stream(stream)))
+    return images
 
 
 def hh_pipeline(p: Params, frames, image, workspace, evals=None, evecs=None, info=None, stream=None):

@@ -107,6 +107,22 @@ class RingPlan:
         """Frames below this index may be written while window next_c is pending."""
         return next_c * self.hop + self.R
 
+    def window_runs(self, cs: List[int], n_images: int) -> List[Tuple[int, int]]:
+        """Runs (first window, count) of the increasing window indices cs that one launch
+        can take: consecutive windows whose frames lie in one contiguous stretch of the
+        hologram ring (mirror copies included) and whose images are contiguous among the
+        n_images buffers."""
+        runs: List[Tuple[int, int]] = []
+        for c in cs:
+            if runs:
+                c0, k = runs[-1]
+                s0 = self.window_slot(c0)
+                if c == c0 + k and s0 + k * self.hop + self.window <= self.slots and c0 % n_images + k < n_images:
+                    runs[-1] = (c0, k + 1)
+                    continue
+            runs.append((c, 1))
+        return runs
+
     def fresnel_runs(self, a: int, b: int) -> List[Tuple[int, int, int]]:
         """Transforms for frames [a, b): (source slot, destination slot, count) runs,
         contiguous in both rings, including the mirror copies."""
@@ -312,8 +328,9 @@ class _Camera:
         self.n_src = source.shape[0]
         self.u16 = torch.empty((ring.R, spec.ny, spec.nx), dtype=torch.uint16, device=device)
         self.holo = torch.empty((ring.slots, spec.ny, spec.nx), dtype=torch.complex64, device=device)
-        self.images = [torch.empty((spec.ny, spec.nx), dtype=torch.float32, device=device)
-                       for _ in range(image_buffers)]
+        # one buffer, so that the images of consecutive windows are contiguous
+        self.image_buf = torch.empty((image_buffers, spec.ny, spec.nx), dtype=torch.float32, device=device)
+        self.images = [self.image_buf[i] for i in range(image_buffers)]
         self.slot_free = [(-1, None)] * ring.R  # (order, compute-stream event after the transform that read it)
         self.last_copy = None                   # copy-stream event after the latest copy
         self.copy_start = {}                    # frame -> event recorded before its copy (latency start)
@@ -442,17 +459,27 @@ class Server:
         import torch
         by_name = {c.spec.name: c for c in self.cams}
         ps, holos, pimgs, imgs = [], [], [], []
+        fourier = {}   # camera -> its ready windows (Eqs. (8)-(9): no covariance, no eigenproblem)
         for name, c in ready:
             cam = by_name[name]
             s = cam.ring.window_slot(c)
             img = cam.images[c % len(cam.images)]
             imgs.append(img)
-            if cam.spec.demod == "fourier":   # Eqs. (8)-(9): no covariance, no eigenproblem
-                hh.hh_fourier_render(cam.p, cam.holo[s:s + cam.spec.window], img, stream=self.compute_stream)
+            if cam.spec.demod == "fourier":
+                fourier.setdefault(name, []).append(c)
             else:
                 ps.append(cam.p)
                 holos.append(cam.holo[s:s + cam.spec.window])
                 pimgs.append(img)
+        for name, cs in fourier.items():
+            # one launch per run of consecutive windows (the frames they share are read once from HBM)
+            cam = by_name[name]
+            n_img = len(cam.images)
+            for c0, k in cam.ring.window_runs(sorted(cs), n_img):
+                s, i0 = cam.ring.window_slot(c0), c0 % n_img
+                frames = (k - 1) * cam.spec.hop + cam.spec.window
+                hh.hh_fourier_render_windows(cam.p, cam.holo[s:s + frames], k, cam.spec.hop,
+                                             cam.image_buf[i0:i0 + k], stream=self.compute_stream)
         if ps:
             hh.hh_analyze_batch(ps, holos, pimgs, self.ws, stream=self.compute_stream)
         done = torch.cuda.Event(enable_timing=True)

@@ -219,6 +219,35 @@ def test_fourier_parity(hh, nt, ny, nx):
         assert rel(to_np(img), R) <= IMG_TOL, (lo, hi)
 
 
+# several windows of a stream in one call: each equals the oracle on its frames and the
+# one-window call bit for bit (power-of-two nt: the per-pixel FFT; 24: the projection)
+@pytest.mark.parametrize("nt,hop,nwin", [(32, 1, 5), (32, 3, 4), (24, 2, 3), (16, 1, 1)])
+def test_fourier_windows_parity(hh, nt, hop, nwin):
+    import ctypes
+    import torch
+    say(f"fourier windows nt={nt} hop={hop} nwin={nwin}")
+    ny, nx = 32, 64
+    n = (nwin - 1) * hop + nt
+    H = oracle.fresnel_ref(gen_stack(5, n, ny, nx), LAM, Z, PITCH).astype(np.complex64)
+    lo, hi = nt // 4, (3 * nt) // 4
+    p = hh.Params(nx=nx, ny=ny, nt=nt, k_lo=lo, k_hi=hi)
+    Hd = to_dev(H)
+    imgs = torch.empty((nwin, ny, nx), dtype=torch.float32, device="cuda")
+    hh.hh_fourier_render_windows(p, Hd, nwin, hop, imgs)
+    got = to_np(imgs)
+    one = torch.empty((ny, nx), dtype=torch.float32, device="cuda")
+    for w in range(nwin):
+        Hw = H[w * hop:w * hop + nt]
+        assert rel(got[w], oracle.fourier_render_ref(Hw.astype(np.complex128), lo, hi)) <= IMG_TOL, w
+        hh.hh_fourier_render(p, to_dev(np.ascontiguousarray(Hw)), one)
+        assert np.array_equal(to_np(one), got[w]), w
+    L = hh.lib()
+    for bad_nwin, bad_hop in ((0, 1), (1, 0)):
+        st = L.hh_fourier_render_windows(ctypes.byref(p.c()), ctypes.c_void_p(Hd.data_ptr()), bad_nwin, bad_hop,
+                                         ctypes.c_void_p(imgs.data_ptr()), None)
+        assert st == hh.HH_E_INVALID
+
+
 def _pipeline(hh, frames, k_lo, k_hi):
     import torch
     nt, ny, nx = frames.shape

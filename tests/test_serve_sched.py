@@ -219,3 +219,25 @@ def test_fourier_camera_needs_no_analysis_workspace():
     b = camera_bytes(F, F.ring(), 4)
     assert b["workspace"] == 0
     assert F.ring().R == 64 and F.ring().slots == 64 + 31
+
+
+@pytest.mark.parametrize("window,hop,ring_hops", [(32, 1, 96), (32, 25, 6), (16, 40, 6), (3, 2, 2)])
+@pytest.mark.parametrize("n_images", [1, 4, 7])
+def test_window_runs_contiguous(window, hop, ring_hops, n_images):
+    # the runs of ready windows rendered by one launch: they partition the ready list,
+    # each run's frames lie in one stretch of the ring (position s0 + j holds frame
+    # c0 hop + j, in its own slot or in a mirror copy) and its images do not wrap
+    r = RingPlan(window, hop, ring_hops)
+    rng = np.random.default_rng(window + hop + n_images)
+    for _ in range(60):
+        start = int(rng.integers(0, 500))
+        cs = sorted({start + int(d) for d in rng.integers(0, 40, size=int(rng.integers(1, 30)))})
+        runs = r.window_runs(cs, n_images)
+        assert [c0 + j for c0, k in runs for j in range(k)] == cs
+        for c0, k in runs:
+            s0 = r.window_slot(c0)
+            assert s0 + (k - 1) * hop + window <= r.slots
+            assert c0 % n_images + k <= n_images
+            for j in range((k - 1) * hop + window):
+                pos, slot = s0 + j, (c0 * hop + j) % r.R
+                assert pos == slot or (pos - r.R == slot and slot < r.M)
