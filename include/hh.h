@@ -442,7 +442,8 @@ hh_status hh_fourier_render(const hh_params *p, const float *holo, float *image,
  * is the band power of hh_fourier_render (equal to it window by window).
  * holo: complex64 [(nwin - 1)*hop + nt][ny][nx] on the device (16-byte aligned);
  * images: float32 [nwin][ny][nx] on the device.  1 <= nwin <= 4096,
- * 1 <= hop <= 4096.  One launch for every window: the frames that consecutive
+ * 1 <= hop <= 4096, else HH_E_INVALID (and the other checks of
+ * hh_fourier_render).  One launch for every window: the frames that consecutive
  * windows share are read from the cache.
  */
 hh_status hh_fourier_render_windows(const hh_params *p, const float *holo, int32_t nwin, int32_t hop, float *images,
