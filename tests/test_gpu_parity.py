@@ -91,6 +91,15 @@ def test_eigh_parity_random(hh, n, solver):
     _eigh_check(hh, C, solver=solver)
 
 
+def test_eigh_every_size(hh):
+    # every n the solver takes (the slot schedule differs with n's parity and size class)
+    say("eigh n=2..64 jacobi")
+    rng = np.random.default_rng(2024)
+    for n in range(2, 65):
+        X = rng.standard_normal((n, n + 2)) + 1j * rng.standard_normal((n, n + 2))
+        _eigh_check(hh, X @ X.conj().T)
+
+
 def _eigh_check(hh, C, sweeps_min=0, solver="jacobi"):
     import torch
     n = C.shape[0]
